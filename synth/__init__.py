@@ -1,0 +1,312 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU library's tests and benchmark.
+
+This module holds no arithmetic of the homogenization method itself: it only draws
+random numbers and lays out microstructures, material constants and load paths.
+
+* Random numbers: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), mapped to [0, 1)
+  as (x >> 11) * 2**-53.
+* Microstructure: periodic Voronoi tessellation of seeded uniform grain centers,
+  distances measured from voxel centers (i + 1/2) with the minimum-image rule,
+  ties resolved to the lowest grain id.  The paper generates its equiaxed RVEs
+  with Dream3D (Section 2.2); those files are not available, so seeded Voronoi
+  RVEs stand in for them.
+* Orientations: uniform random rotations drawn as unit quaternions with
+  Shoemake's method (Graphics Gems III, 1992), stored (w, x, y, z) and mapping
+  the crystal frame to the sample frame.
+* Materials: elastic constants of the workloads (Cu, Al, Ag, Ni), the dislocation
+  parameters of Table 2 and the common parameters of Table 1.
+* Load path: uniaxial tension along x at constant engineering strain rate
+  (Section 3): F_11(t) = 1 + rate * t, shear components held at zero, lateral
+  normal stresses P_22 = P_33 = 0.
+
+Voxel arrays are shaped (nz, ny, nx) so that the flat C-order index has x fastest.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 generator (Steele, Lea & Flood 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+    def uniforms(self, n: int) -> np.ndarray:
+        return np.array([self.uniform() for _ in range(n)], dtype=np.float64)
+
+
+def shoemake_quaternions(rng: SplitMix64, n: int) -> np.ndarray:
+    """n uniform random unit quaternions (w, x, y, z), three draws each."""
+    q = np.empty((n, 4))
+    for g in range(n):
+        u1, u2, u3 = rng.uniform(), rng.uniform(), rng.uniform()
+        a, b = math.sqrt(1.0 - u1), math.sqrt(u1)
+        t2, t3 = 2.0 * math.pi * u2, 2.0 * math.pi * u3
+        q[g] = (b * math.cos(t3), a * math.sin(t2), a * math.cos(t2), b * math.sin(t3))
+    return q
+
+
+def grain_centers(rng: SplitMix64, n_grains: int, n: Sequence[int]) -> np.ndarray:
+    """Uniform centers in [0, n_x) x [0, n_y) x [0, n_z), voxel units, (x, y, z) per row."""
+    c = np.empty((n_grains, 3))
+    for g in range(n_grains):
+        for d in range(3):
+            c[g, d] = rng.uniform() * n[d]
+    return c
+
+
+def periodic_voronoi(n: Sequence[int], centers: np.ndarray) -> np.ndarray:
+    """Grain id per voxel, shape (nz, ny, nx), int32.
+
+    Distance from the voxel center (i + 1/2) to each grain center with the
+    periodic minimum-image convention; np.argmin keeps the lowest id on ties.
+    """
+    nx, ny, nz = int(n[0]), int(n[1]), int(n[2])
+    out = np.empty((nz, ny, nx), dtype=np.int32)
+    xs = np.arange(nx) + 0.5
+    ys = np.arange(ny) + 0.5
+
+    def wrap(d, L):
+        d = np.abs(d)
+        return np.minimum(d, L - d)
+
+    dx = wrap(xs[None, :] - centers[:, 0:1], nx) ** 2          # (G, nx)
+    dy = wrap(ys[None, :] - centers[:, 1:2], ny) ** 2          # (G, ny)
+    for k in range(nz):
+        dz = wrap((k + 0.5) - centers[:, 2], nz) ** 2          # (G,)
+        d2 = dz[:, None, None] + dy[:, :, None] + dx[:, None, :]  # (G, ny, nx)
+        out[k] = np.argmin(d2, axis=0).astype(np.int32)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Materials.  Elastic constants in Pa, lengths in m.
+# --------------------------------------------------------------------------------------
+# Table 1 (common to all FCC crystals): reference slip rate, rate sensitivity and the six
+# interaction coefficients (self, coplanar, collinear, Hirth, glissile, Lomer).
+TABLE1_GAMMA0_DOT = 1.0e-3
+TABLE1_M = 0.05
+TABLE1_Q = (0.122, 0.122, 0.657, 0.084, 0.137, 0.118)
+
+# Table 2 dislocation parameters: Burgers vector, effective annihilation distance y_c,
+# similitude coefficient K.
+TABLE2_DISLOCATION = {
+    "Cu": (0.256e-9, 15.0e-9, 6.0),
+    "Al": (0.286e-9, 56.0e-9, 9.0),
+    "Ni": (0.250e-9, 14.0e-9, 11.0),
+    "Ag": (0.288e-9, 12.5e-9, 5.0),
+}
+# Table 2 elastic constants (C11, C12, C44) and the printed slip-plane shear modulus.
+TABLE2_ELASTIC = {
+    "Cu": (169e9, 122e9, 75.3e9),
+    "Al": (108e9, 61.3e9, 28.0e9),
+    "Ni": (249e9, 155e9, 114e9),
+    "Ag": (124e9, 93.7e9, 46.1e9),
+}
+TABLE2_MU = {"Cu": 30.5e9, "Al": 25.0e9, "Ni": 58.4e9, "Ag": 19.5e9}
+# Elastic constants of the benchmark workloads (they differ slightly from Table 2).
+WORKLOAD_ELASTIC = {
+    "Cu": (168.4e9, 121.4e9, 75.4e9),
+    "Al": (108e9, 62e9, 28.3e9),
+    "Ag": (124e9, 93.4e9, 46.1e9),
+    "Ni": (246.5e9, 147.3e9, 124.7e9),
+}
+
+
+@dataclasses.dataclass
+class Material:
+    C11: float
+    C12: float
+    C44: float
+    burgers: float
+    y_c: float
+    K_sim: float
+    gamma0_dot: float = TABLE1_GAMMA0_DOT
+    m_rate: float = TABLE1_M
+    q: tuple = TABLE1_Q
+    tau0: float = 0.0      # Pa; > 0: sets the initial SSD density per system
+    rho0: float = 0.0      # 1/m^2 per system; used when > 0 (overrides tau0)
+    c_gnd: float = 1.0     # weight of the GND density in the hardening law (0: no gradient)
+    hardening: int = 1     # 1: Taylor/Kocks-Mecking hardening; 0: tau_c frozen at tau0
+    mu: float = 0.0        # Pa; <= 0: computed from the cubic constants
+
+    def replace(self, **kw) -> "Material":
+        return dataclasses.replace(self, **kw)
+
+
+def material(name: str, elastic: str = "workload", **kw) -> Material:
+    C = (WORKLOAD_ELASTIC if elastic == "workload" else TABLE2_ELASTIC)[name]
+    b, yc, K = TABLE2_DISLOCATION[name]
+    return Material(C11=C[0], C12=C[1], C44=C[2], burgers=b, y_c=yc, K_sim=K, **kw)
+
+
+# --------------------------------------------------------------------------------------
+# RVEs and load paths
+# --------------------------------------------------------------------------------------
+@dataclasses.dataclass
+class RVE:
+    n: tuple                 # (nx, ny, nz)
+    voxel_size: float        # h, m
+    grain_of_voxel: np.ndarray  # (nz, ny, nx) int32
+    quats: np.ndarray        # (n_grains, 4) (w, x, y, z), crystal -> sample
+    material: Material
+    seed: int = 0
+
+    @property
+    def n_grains(self) -> int:
+        return self.quats.shape[0]
+
+    @property
+    def n_vox(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+
+def voronoi_rve(seed: int, n, n_grains: int, voxel_size: float, mat: Material) -> RVE:
+    """Seeded periodic Voronoi RVE: 3 draws per grain center, then 3 per orientation."""
+    n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n, n, n)))
+    rng = SplitMix64(seed)
+    centers = grain_centers(rng, n_grains, n)
+    quats = shoemake_quaternions(rng, n_grains)
+    gid = periodic_voronoi(n, centers)
+    return RVE(n=n, voxel_size=voxel_size, grain_of_voxel=gid, quats=quats, material=mat, seed=seed)
+
+
+def single_crystal_rve(n, quat, mat: Material, voxel_size: float = 1e-6) -> RVE:
+    n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n, n, n)))
+    gid = np.zeros((n[2], n[1], n[0]), dtype=np.int32)
+    return RVE(n=n, voxel_size=voxel_size, grain_of_voxel=gid,
+               quats=np.asarray(quat, dtype=np.float64).reshape(1, 4), material=mat)
+
+
+def laminate_rve(n, n_layers_a: int, quat_a, quat_b, mat: Material, voxel_size: float = 1e-6) -> RVE:
+    """Two grains stacked along z: layers k < n_layers_a are grain 0, the rest grain 1."""
+    n = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n, n, n)))
+    gid = np.ones((n[2], n[1], n[0]), dtype=np.int32)
+    gid[:n_layers_a] = 0
+    quats = np.stack([np.asarray(quat_a, float), np.asarray(quat_b, float)])
+    return RVE(n=n, voxel_size=voxel_size, grain_of_voxel=gid, quats=quats, material=mat)
+
+
+# Uniaxial tension along x: F-controlled 11,12,13,21,23,31,32; P-controlled 22, 33.
+UNIAXIAL_MASK = np.array([1, 1, 1, 1, 0, 1, 1, 1, 0], dtype=np.uint8)
+
+
+@dataclasses.dataclass
+class LoadPath:
+    F_bar: np.ndarray   # (n_inc + 1, 9) macroscopic F targets (row-major), index 0 = t0
+    P_bar: np.ndarray   # (n_inc + 1, 9) macroscopic P targets where mask == 0
+    mask: np.ndarray    # (9,) uint8, 1 = F-controlled
+    dt: float
+
+    @property
+    def n_inc(self) -> int:
+        return self.F_bar.shape[0] - 1
+
+
+def uniaxial_tension(strain_max: float, n_inc: int, rate: float) -> LoadPath:
+    dt = strain_max / (n_inc * rate)
+    F = np.tile(np.eye(3).reshape(9), (n_inc + 1, 1))
+    F[:, 0] = 1.0 + rate * dt * np.arange(n_inc + 1)
+    return LoadPath(F_bar=F, P_bar=np.zeros((n_inc + 1, 9)), mask=UNIAXIAL_MASK.copy(), dt=dt)
+
+
+# --------------------------------------------------------------------------------------
+# The benchmark workloads
+# --------------------------------------------------------------------------------------
+def voxel_size_for(d: float, n_grains: int, n: int) -> float:
+    """Grain size d read as L / n_grains^(1/3): voxel size h = d * n_grains^(1/3) / n."""
+    return d * n_grains ** (1.0 / 3.0) / n
+
+
+C4_SIZES = (32, 40, 48, 64, 72, 80, 96)
+C4_MATERIALS = ("Cu", "Ag", "Ni")
+
+
+def workload(name: str, n_override=None, n_inc_override=None):
+    """Return (list of RVEs, LoadPath, description) for a named benchmark workload.
+
+    c1: 16^3, 8 grains, Cu, tau0 = 10 MPa, no gradient term, 1% in 20 increments at 1e-3/s.
+    c2: 64^3, 64 grains, Cu, d = 50 um, rho_i = 1.2e12 (1e11 per system), 5% in 50 at 1e-4/s.
+    c3: 128^3, 200 grains, Al, d = 20 um, 5% in 50 increments at 1e-4/s.
+    c4: 32 RVEs of uneven size (32^3..96^3), 16..128 grains, d log-uniform in [10, 200] um,
+        Cu/Ag/Ni, 3% in 30 increments at 1e-4/s.
+    c5: 64^3, 100 grains, Cu, d = 30 um, 4% in 40 increments at 1e-4/s.
+    """
+    if name == "c1":
+        n = n_override or 16
+        mat = material("Cu", tau0=10e6, c_gnd=0.0)
+        rves = [voronoi_rve(101, n, 8, voxel_size_for(50e-6, 8, n), mat)]
+        path = uniaxial_tension(0.01, n_inc_override or 20, 1e-3)
+    elif name == "c2":
+        n = n_override or 64
+        mat = material("Cu", rho0=1e11, c_gnd=1.0)
+        rves = [voronoi_rve(102, n, 64, voxel_size_for(50e-6, 64, n), mat)]
+        path = uniaxial_tension(0.05, n_inc_override or 50, 1e-4)
+    elif name == "c3":
+        n = n_override or 128
+        mat = material("Al", rho0=1e11, c_gnd=1.0)
+        rves = [voronoi_rve(103, n, 200, voxel_size_for(20e-6, 200, n), mat)]
+        path = uniaxial_tension(0.05, n_inc_override or 50, 1e-4)
+    elif name == "c4":
+        rves = []
+        for r in range(32):
+            rng = SplitMix64(1040 + r)
+            nr = C4_SIZES[min(int(rng.uniform() * len(C4_SIZES)), len(C4_SIZES) - 1)]
+            ng = 16 + min(int(rng.uniform() * 113), 112)
+            d = 10e-6 * math.exp(rng.uniform() * math.log(20.0))
+            if n_override:
+                nr = n_override
+            mat = material(C4_MATERIALS[r % 3], rho0=1e11, c_gnd=1.0)
+            centers = grain_centers(rng, ng, (nr, nr, nr))
+            quats = shoemake_quaternions(rng, ng)
+            gid = periodic_voronoi((nr, nr, nr), centers)
+            rves.append(RVE(n=(nr, nr, nr), voxel_size=voxel_size_for(d, ng, nr),
+                            grain_of_voxel=gid, quats=quats, material=mat, seed=1040 + r))
+        path = uniaxial_tension(0.03, n_inc_override or 30, 1e-4)
+    elif name == "c5":
+        n = n_override or 64
+        mat = material("Cu", rho0=1e11, c_gnd=1.0)
+        rves = [voronoi_rve(105, n, 100, voxel_size_for(30e-6, 100, n), mat)]
+        path = uniaxial_tension(0.04, n_inc_override or 40, 1e-4)
+    else:
+        raise ValueError(name)
+    return rves, path
+
+
+def random_deformations(seed: int, count: int, amplitude: float) -> np.ndarray:
+    """count near-identity deformation gradients I + amplitude * U(-1, 1), row-major (count, 9)."""
+    rng = SplitMix64(seed)
+    u = rng.uniforms(9 * count).reshape(count, 9)
+    return np.eye(3).reshape(1, 9) + amplitude * (2.0 * u - 1.0)
+
+
+def random_field(seed: int, shape, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Uniform random array from SplitMix64 (vectorised through numpy for size)."""
+    rng = SplitMix64(seed)
+    n = int(np.prod(shape))
+    # draw 64-bit words in bulk: numpy reproduction of SplitMix64 on a counter
+    base = (rng.state + 0x9E3779B97F4A7C15 * (np.arange(1, n + 1, dtype=np.uint64))).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        z = base
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (lo + (hi - lo) * u).reshape(shape)

@@ -1,0 +1,100 @@
+"""Pins of the oracle's material point (Section 2.1, eqs. 1-9, 14)."""
+import numpy as np
+
+import synth
+from oracle import constitutive as cst
+from oracle import elasticity, reference
+
+
+def _setup(V=12, amp=3e-4, seed=3, c_gnd=1.0):
+    mat = synth.material("Cu", tau0=10e6, c_gnd=c_gnd)
+    q = synth.shoemake_quaternions(synth.SplitMix64(seed), 4)
+    model = cst.MaterialModel(mat, q)
+    gid = np.arange(V) % 4
+    F = synth.random_deformations(seed + 1, V, amp).reshape(V, 3, 3)
+    Fp_n = synth.random_deformations(seed + 2, V, 2e-4).reshape(V, 3, 3)
+    rs = model.rho0 * (1 + synth.random_field(seed + 3, (V, 12), 0, 1))
+    rg = synth.random_field(seed + 4, (V, 12), 0, 1) * 1e12
+    return mat, model, gid, F, Fp_n, rs, rg
+
+
+def test_elastic_limit_is_st_venant_kirchhoff():
+    """tau0 -> huge: no slip, Fp = Fp_n = I, and eq. 14 reduces to P = F (C : E)."""
+    mat = synth.material("Al", tau0=1e14, c_gnd=0.0)
+    q = synth.shoemake_quaternions(synth.SplitMix64(4), 3)
+    model = cst.MaterialModel(mat, q)
+    V = 9
+    F = synth.random_deformations(5, V, 5e-3).reshape(V, 3, 3)
+    gid = np.arange(V) % 3
+    out = cst.update(model, gid, F, np.tile(np.eye(3), (V, 1, 1)), np.full((V, 12), model.rho0),
+                     np.zeros((V, 12)), 1.0, np.zeros((V, 12)))
+    P_ref = reference.svk_stress(F, model.C[gid])
+    assert np.allclose(out["P"], P_ref, rtol=1e-12, atol=1e-6)
+    assert np.abs(out["dg"]).max() < 1e-100
+
+
+def test_converged_slip_solves_flow_rule_and_shares_root():
+    mat, model, gid, F, Fp_n, rs, rg = _setup()
+    dt = 0.5
+    out = cst.update(model, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    assert out["converged"].all()
+    pd = cst.PointData(model, gid, Fp_n, rs, rg)
+    R = cst.residual(pd, F, out["dg"], dt)
+    assert np.all(np.abs(R).max(axis=1) <= 1e-10 * np.abs(out["dg"]).max(axis=1))
+    # flow rule written out independently from the stress of the returned state
+    tau = np.einsum("vij,vaij->va", out["S"], model.P0[gid])
+    g = dt * mat.gamma0_dot * (np.abs(tau) / out["tau_c"]) ** (1 / mat.m_rate) * np.sign(tau)
+    assert np.allclose(g, out["dg"], rtol=1e-8, atol=1e-18)
+    # a different starting point reaches the same root
+    out2 = cst.update(model, gid, F, Fp_n, rs, rg, dt, 1e-4 * np.ones_like(rs))
+    assert np.allclose(out2["dg"], out["dg"], rtol=1e-9, atol=1e-16)
+    assert np.allclose(out2["P"], out["P"], rtol=1e-11)
+
+
+def test_state_update_formulas():
+    """Fp = (I + sum dg s(x)m) Fp_n (eq. 2, backward Euler); Fe = F Fp^-1; rho_SSD by eq. 8;
+    tau_c by eq. 7 with the forest densities; P from S by eq. 14."""
+    mat, model, gid, F, Fp_n, rs, rg = _setup()
+    out = cst.update(model, gid, F, Fp_n, rs, rg, 0.5, np.zeros_like(rs))
+    s0, m0 = __import__("oracle.tables", fromlist=["x"]).slip_systems()
+    R = model.R[gid]
+    s = np.einsum("vij,aj->vai", R, s0)
+    m = np.einsum("vij,aj->vai", R, m0)
+    L = np.einsum("va,vai,vaj->vij", out["dg"], s, m)
+    assert np.allclose(out["Fp"], (np.eye(3) + L) @ Fp_n, rtol=1e-14)
+    Fe = F @ np.linalg.inv(out["Fp"])
+    assert np.allclose(out["P"], Fe @ out["S"] @ np.linalg.inv(out["Fp"]).transpose(0, 2, 1), rtol=1e-10)
+    q = model.q
+    forest = rs + mat.c_gnd * rg
+    ell = mat.K_sim / np.sqrt(forest.sum(1, keepdims=True) - forest)
+    rho_new = rs + (1 / mat.burgers) * (1 / ell - 2 * mat.y_c * rs) * np.abs(out["dg"])
+    assert np.allclose(out["rho_ssd"], rho_new, rtol=1e-14)
+    mu = elasticity.slip_plane_shear_modulus(mat.C11, mat.C12, mat.C44)
+    assert np.allclose(out["tau_c"], mu * mat.burgers * np.sqrt(forest @ q.T), rtol=1e-14)
+
+
+def test_fd_tangent_step_consistency():
+    mat, model, gid, F, Fp_n, rs, rg = _setup(V=4)
+    dt = 0.5
+    out = cst.update(model, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    K1 = cst.tangent_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], step=1e-8)
+    K2 = cst.tangent_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], step=4e-8)
+    assert np.abs(K1 - K2).max() / np.abs(K1).max() < 1e-5
+
+
+def test_schmid_single_crystal_steady_flow():
+    """[100] single crystal, hardening off: 8 systems with Schmid factor 1/sqrt(6) carry the
+    plastic strain rate, so steady flow has S_xx = (tau0/M) (rate / (8 M gdot0))^m
+    (23.087 MPa for tau0 = 10 MPa, rate = gdot0 = 1e-3/s)."""
+    mat = synth.material("Cu", tau0=10e6, c_gnd=0.0, hardening=0)
+    path = synth.uniaxial_tension(0.01, 20, 1e-3)
+    res = reference.material_point_path(mat, [1, 0, 0, 0], path)
+    M = 1 / np.sqrt(6)
+    expect = (10e6 / M) * (1e-3 / (8 * M * 1e-3)) ** 0.05
+    assert abs(expect / 23.087e6 - 1) < 1e-4
+    S_last = res[-1][2]
+    assert abs(S_last[0, 0] / expect - 1) < 1.5e-3
+    tau = np.abs(res[-1][3])
+    assert np.sum(tau > 0.9 * tau.max()) == 8
+    # the lateral stresses vanish
+    assert abs(res[-1][1][1, 1]) < 1e-3 and abs(res[-1][1][2, 2]) < 1e-3

@@ -1,0 +1,131 @@
+"""Pins of the oracle's Galerkin-FFT homogenization (Section 2.2, eqs. 15-18) against
+solutions that do not use the FFT projection."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import elasticity, nye, reference, solver, spectral
+
+
+def test_homogeneous_single_grain_equals_material_point():
+    mat = synth.material("Cu", tau0=10e6, c_gnd=1.0)
+    q = synth.shoemake_quaternions(synth.SplitMix64(21), 1)[0]
+    rve = synth.single_crystal_rve((2, 3, 2), q, mat)
+    path = synth.uniaxial_tension(0.004, 4, 1e-3)
+    s = solver.RVESolver(rve)
+    recs = s.run(path)
+    ref = reference.material_point_path(mat, q, path)
+    for rec, (F, P, S, tau) in zip(recs, ref):
+        assert np.allclose(np.array(rec["P_avg"]).reshape(3, 3), P, rtol=1e-9, atol=1e-3)
+        assert np.allclose(np.array(rec["F_avg"]).reshape(3, 3), F, rtol=1e-12, atol=1e-13)
+    assert np.abs(s.F - s.F.mean(0)).max() < 1e-13           # uniform field
+    assert np.abs(s.rho_gnd).max() < 1e-3                      # uniform Fp: no GND
+
+
+@pytest.mark.parametrize("plastic", [False, True])
+def test_laminate_matches_piecewise_uniform_solution(plastic):
+    qa = synth.shoemake_quaternions(synth.SplitMix64(31), 2)
+    if plastic:
+        mat = synth.material("Cu", tau0=8e6, c_gnd=0.0)
+        path = synth.uniaxial_tension(0.002, 3, 1e-3)
+    else:
+        mat = synth.material("Ni", tau0=1e14, c_gnd=0.0)
+        path = synth.uniaxial_tension(0.003, 2, 1e-3)
+    n_a, nz = 3, 8
+    rve = synth.laminate_rve((2, 2, nz), n_a, qa[0], qa[1], mat)
+    s = solver.RVESolver(rve)
+    recs = s.run(path)
+    ref = reference.laminate_path(mat, qa[0], qa[1], n_a / nz, path, elastic_svk=not plastic)
+    Fa, Fb, Pa, Pb = ref[-1]
+    F = s.field(s.F)
+    P = s.field(s.P)
+    assert np.allclose(F[:n_a], Fa, rtol=0, atol=2e-12)
+    assert np.allclose(F[n_a:], Fb, rtol=0, atol=2e-12)
+    scale = np.abs(Pa).max()
+    assert np.allclose(P[:n_a], Pa, atol=1e-8 * scale)
+    assert np.allclose(P[n_a:], Pb, atol=1e-8 * scale)
+
+
+def test_linear_elastic_solve_matches_dense_galerkin_assembly():
+    """4x4x4, two grains, small-strain linear elasticity: one projected CG solve from F_bar
+    equals the real-space Galerkin least-squares solution."""
+    shape = (4, 4, 4)
+    rve = synth.voronoi_rve(41, (4, 4, 4), 2, 1e-6, synth.material("Cu"))
+    R = elasticity.quat_to_matrix(rve.quats)
+    C0 = elasticity.cubic_stiffness(*synth.WORKLOAD_ELASTIC["Cu"])
+    C = elasticity.rotate4(C0, R)[rve.grain_of_voxel]                    # (4,4,4,3,3,3,3)
+    F_bar = np.array([[1e-3, 2e-4, 0], [0, -3e-4, 1e-4], [5e-5, 0, 4e-4]])
+    F_ref = reference.dense_galerkin_elastic(C, F_bar)
+    V = 64
+    Cf = C.reshape(V, 3, 3, 3, 3)
+    mask = np.ones(9)
+
+    def apply(x):
+        y = np.einsum("vijkl,vkl->vij", Cf, x)
+        return spectral.project(y.reshape(shape + (3, 3)), mask).reshape(V, 3, 3)
+
+    b = -apply(np.broadcast_to(F_bar, (V, 3, 3)).copy())
+    dF, it = solver.conjugate_gradient(apply, b, 1e-14, 2000)
+    F = F_bar + dF
+    assert np.allclose(F.reshape(shape + (3, 3)), F_ref, rtol=0, atol=1e-15 + 1e-11 * np.abs(F_bar).max())
+
+
+@pytest.fixture(scope="module")
+def small_run():
+    rves, path = synth.workload("c2", n_override=6, n_inc_override=50)
+    rve = rves[0]
+    rve.voxel_size = 5e-7
+    s = solver.RVESolver(rve)
+    recs = s.run(path, n_inc=2)
+    return rve, path, s, recs
+
+
+def test_converged_field_is_compatible_and_in_equilibrium(small_run):
+    rve, path, s, recs = small_run
+    F = s.field(s.F)
+    P = s.field(s.P)
+    # compatibility: F - <F> is a discrete gradient, so its discrete curl vanishes
+    curlF = spectral.curl(F - F.mean(axis=(0, 1, 2)) + np.eye(3), 1.0)
+    assert np.abs(curlF).max() < 1e-13
+    # equilibrium and mixed control
+    r = spectral.project(P, path.mask, path.P_bar[2].reshape(3, 3))
+    assert np.abs(r).max() < 1e-9 * np.abs(P).max()
+    m = path.mask.reshape(3, 3)
+    assert np.allclose(F.mean(axis=(0, 1, 2)) * m, path.F_bar[2].reshape(3, 3) * m, atol=1e-14)
+    assert np.all(np.abs(P.mean(axis=(0, 1, 2)) * (1 - m)) < 1e-9 * np.abs(P).max())
+
+
+def test_gnd_recomputed_from_committed_fp(small_run):
+    rve, path, s, recs = small_run
+    alpha, seg, rho = nye.gnd_from_fp(s.field(s.Fp), rve.voxel_size, rve.grain_of_voxel,
+                                      rve.quats, rve.material.burgers)
+    assert np.allclose(s.field(s.rho_gnd), rho)
+    assert rho.max() > 0
+    # alpha scales as 1/h for a fixed Fp
+    a2 = nye.nye_tensor(s.field(s.Fp), 2 * rve.voxel_size)
+    assert np.allclose(a2, alpha / 2)
+
+
+def test_periodic_translation_equivariance():
+    rves, path = synth.workload("c1", n_override=4)
+    rve = rves[0]
+    s1 = solver.RVESolver(rve)
+    r1 = s1.run(path, n_inc=2)
+    shifted = synth.RVE(n=rve.n, voxel_size=rve.voxel_size,
+                        grain_of_voxel=np.roll(rve.grain_of_voxel, (1, 2, 3), axis=(0, 1, 2)),
+                        quats=rve.quats, material=rve.material)
+    s2 = solver.RVESolver(shifted)
+    r2 = s2.run(path, n_inc=2)
+    scale = np.abs(r1[-1]["P_avg"]).max()
+    assert np.allclose(r1[-1]["P_avg"], r2[-1]["P_avg"], rtol=0, atol=1e-10 * scale)
+    assert np.allclose(np.roll(s1.field(s1.F), (1, 2, 3), axis=(0, 1, 2)), s2.field(s2.F), atol=1e-12)
+
+
+def test_without_gradient_term_voxel_size_does_not_matter():
+    rves, path = synth.workload("c1", n_override=4)
+    rve = rves[0]
+    out = []
+    for h in (1e-6, 3e-5):
+        rve.voxel_size = h
+        out.append(solver.RVESolver(rve).run(path, n_inc=2)[-1]["P_avg"])
+    assert np.allclose(out[0], out[1], rtol=0, atol=1e-11 * np.abs(out[0]).max())
