@@ -1,0 +1,184 @@
+/*
+ * rve.h -- C ABI of the MI355X (gfx950) library for FFT-based strain-gradient
+ * crystal-plasticity homogenization of periodic FCC polycrystal RVEs.
+ *
+ * Method: Haouala, Lucarini, LLorca, Segurado, "Simulation of the Hall-Petch effect in
+ * FCC polycrystals by means of strain gradient crystal plasticity and FFT
+ * homogenization" (arXiv 1910.01946).  Section numbers and equation numbers below
+ * refer to that paper.
+ *
+ * Conventions shared by every call
+ *  - Units: SI (Pa, m, s, 1/m^2).
+ *  - Tensors are row-major 3x3 (component ij at index 3*i + j); x, y, z = 0, 1, 2.
+ *  - Voxel fields are component-major ("SoA"): field[c * nvox + v] with the voxel index
+ *    v = (z * ny + y) * nx + x (x fastest).
+ *  - Every call returns an rve_status; 0 is success.  A failing call leaves the handle's
+ *    committed state unchanged and stores a message readable with rve_last_error().
+ *  - Host pointers are read during the call only (inputs are copied); output host
+ *    buffers are owned and sized by the caller.  Pointers documented as "device" must
+ *    point to memory of the handle's device (for instance from torch tensors on cuda:0).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef RVE_H
+#define RVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rve_ctx* rve_handle;
+
+enum {
+  RVE_OK = 0,
+  RVE_EINVAL = -1,   /* bad argument: shape, non-finite value, dt <= 0, unknown index   */
+  RVE_ENOMEM = -2,   /* device allocation failed                                       */
+  RVE_EDEVICE = -3,  /* a HIP runtime call failed                                      */
+  RVE_ENOCONV = -4,  /* Newton / CG / local update did not converge; state rolled back */
+  RVE_ESTATE = -5    /* call not valid in the current state                            */
+};
+
+enum { RVE_FP64 = 0, RVE_MIXED = 1 };
+
+/* Single-crystal parameters (Section 2.1; Tables 1 and 2). */
+typedef struct {
+  double C11, C12, C44;  /* cubic elastic constants in the crystal frame, Pa (eq. 4)            */
+  double mu;             /* Taylor shear modulus, Pa (eq. 7); <= 0 selects the {111}<110> shear
+                            modulus 3 C44 (C11-C12) / (C11-C12+4 C44) (Table 2's mu)           */
+  double burgers;        /* Burgers vector magnitude b, m (eqs. 7, 8, 13)                      */
+  double y_c;            /* effective annihilation distance, m (eq. 8)                         */
+  double K_sim;          /* similitude coefficient K (eq. 9)                                   */
+  double gamma0_dot;     /* reference slip rate, 1/s (eq. 6)                                   */
+  double m_rate;         /* rate sensitivity m; the flow-rule exponent is 1/m (eq. 6)          */
+  double q[6];           /* interaction coefficients: self, coplanar, collinear, Hirth,
+                            glissile, Lomer (Table 1, eq. 7)                                  */
+  double tau0;           /* Pa: initial critical stress; sets the uniform initial SSD density
+                            rho0 = (tau0 / (mu b))^2 / sum_b q^{ab} (used when rho0 <= 0)      */
+  double rho0;           /* initial SSD density per slip system, 1/m^2 (> 0 overrides tau0)   */
+  double c_gnd;          /* weight of the GND density in eqs. 7 and 9 (1: the paper's model,
+                            0: no gradient term, the paper's "infinite grain size")          */
+  int32_t hardening;     /* 1: tau_c from the dislocation densities (eqs. 7-9);
+                            0: tau_c fixed at tau0 and densities frozen                        */
+} rve_material;
+
+/* One RVE: a periodic voxel grid with a grain map (Section 2.2). */
+typedef struct {
+  int32_t n[3];                  /* voxels along x, y, z; each 1..256 with prime factors 2, 3, 5  */
+  double voxel_size;             /* h, m: sets the length scale of the Nye tensor (eq. 12)       */
+  int32_t n_grains;
+  const int32_t* grain_of_voxel; /* host, nvox entries in [0, n_grains); copied                  */
+  const double* grain_quat;      /* host, n_grains x (w, x, y, z), crystal -> sample; copied and
+                                    normalised                                                  */
+  rve_material material;         /* by value                                                     */
+} rve_desc;
+
+typedef struct {
+  int32_t precision;     /* RVE_FP64: every step in FP64.  RVE_MIXED: FFTs, projection,
+                            conjugate-gradient vectors and the tangent copy in FP32; the
+                            constitutive update, F, Fp and the macroscopic averages in FP64 */
+  double newton_tol;     /* stop an increment once the rms of the applied correction dF is
+                            below this value                                                 */
+  double cg_tol;         /* relative residual of the conjugate-gradient solve of eq. 18      */
+  int32_t max_newton;    /* Newton iterations per increment                                  */
+  int32_t max_cg;        /* CG iterations per Newton iteration                               */
+  int32_t max_backtrack; /* halvings of a Newton step in the residual line search            */
+  int32_t device;        /* HIP device ordinal                                               */
+  void* stream;          /* hipStream_t to run on (for instance torch.cuda.current_stream());
+                            NULL: the library's own stream                                   */
+} rve_options;
+
+/* Per-RVE statistics of one increment. */
+typedef struct {
+  int32_t status;            /* rve_status of this RVE                                          */
+  int32_t newton_iters;      /* Newton corrections applied                                      */
+  int32_t cg_iters;          /* conjugate-gradient iterations (one projected apply each)        */
+  int32_t residual_evals;    /* projected residual evaluations (one projected apply each)       */
+  int32_t line_search_cuts;  /* step halvings in the residual line search                       */
+  int32_t local_iters_max;   /* largest local Newton iteration count of any voxel               */
+  double res_norm;           /* rms of the final projected residual G(P - P_bar), Pa           */
+  double dF_norm;            /* rms of the last applied correction                              */
+  double voxel_iterations;   /* nvox * (residual_evals + cg_iters)                              */
+} rve_step_stats;
+
+/* Create a handle holding n_rve RVEs (Section 2.2).  Per grain: rotation from the
+ * quaternion, slip systems s = R s0, m = R m0 (12 {111}<110>), interaction matrix q
+ * (Table 1 classes), segment matrix A and its minimum-norm inverse (eq. 13).
+ * State: F = Fp = I, rho_SSD = rho0, rho_GND = 0.  opt may be NULL (defaults:
+ * RVE_FP64, newton_tol 1e-10, cg_tol 1e-8, max_newton 40, max_cg 2000, max_backtrack 12,
+ * device 0, own stream).  Errors: RVE_EINVAL (bad shape, grain id out of range,
+ * non-finite or non-positive material constant, zero initial density), RVE_ENOMEM,
+ * RVE_EDEVICE. */
+int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt, rve_handle* out);
+
+/* Advance every RVE by one load increment of length dt (Section 2.2, eqs. 15-18):
+ * mixed control with mask[9] (1 = average of F_ij prescribed by F_bar, 0 = average of
+ * P_ij prescribed by P_bar); F_bar, P_bar are n_rve x 9 (host).  Solves
+ * G(P(F) - P_bar) = 0 by Newton with conjugate-gradient linear solves of eq. 18 and a
+ * residual line search, commits Fp and rho_SSD, then computes the Nye tensor of Fp
+ * (eq. 12, Appendix B) and the GND densities (eq. 13) used by the next increment.
+ * stats: n_rve entries or NULL.  Errors: RVE_EINVAL (dt <= 0, non-finite target);
+ * RVE_ENOCONV if any RVE fails (its stats entry says which; no RVE is committed). */
+int32_t rve_step_increment(rve_handle h, const double* F_bar, const uint8_t* mask,
+                           const double* P_bar, double dt, rve_step_stats* stats);
+
+/* Nye tensor (eq. 12; 1/m, 9 x nvox) and GND density per slip system (eq. 13;
+ * 1/m^2, 12 x nvox) of the last committed increment, copied to host buffers; either
+ * pointer may be NULL.  Errors: RVE_EINVAL for a bad rve index. */
+int32_t rve_nye_gnd(rve_handle h, int32_t rve, double* nye, double* rho_gnd);
+
+/* Volume averages <P>, <F> (eq. 15) of the last committed increment, accumulated in
+ * FP64, and the macroscopic Cauchy stress <P><F>^T / det<F>; each a host array of 9,
+ * sigma may be NULL. */
+int32_t rve_macro_stress(rve_handle h, int32_t rve, double* P_avg, double* F_avg, double* sigma);
+
+/* Copy a committed field to a host buffer: which = 0 F (9), 1 P (9), 2 Fp (9),
+ * 3 rho_SSD (12), 4 rho_GND (12), 5 Nye tensor (9), 6 slip increments of the last
+ * increment (12).  Component-major, nvox per component. */
+int32_t rve_get_field(rve_handle h, int32_t rve, int32_t which, double* out);
+
+/* Save / restore the committed state of every RVE (F, Fp, rho_SSD, rho_GND, Nye, slip
+ * increments, P and the previous increment's F) byte-exactly.  rve_state_bytes gives
+ * the size of the host buffer. */
+int64_t rve_state_bytes(rve_handle h);
+int32_t rve_save_state(rve_handle h, void* buf);
+int32_t rve_load_state(rve_handle h, const void* buf);
+
+void rve_destroy(rve_handle h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rve_last_error(void);
+
+/* ---- Kernel-level entry points (device pointers; used by tests and benchmarks) ---- */
+
+/* Constitutive update (Section 2.1, eqs. 1-9, 14) of nvox independent material points
+ * on the device.  Inputs (device, component-major): gid (nvox int32), F (9), Fp_n (9),
+ * rho_ssd_n (12), rho_gnd_n (12); dg (12) holds the starting slip increments and
+ * receives the converged ones.  Outputs (device): P (9, FP64), K (81 = dP_ij/dF_kl at
+ * index (3i+j)*9 + (3k+l), FP64; NULL to skip), local iteration count per voxel (int32;
+ * negative if that voxel did not converge; may be NULL).  Grain rotations come from
+ * n_grains host quaternions.  stream: hipStream_t or NULL. */
+int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const double* grain_quat,
+                               int64_t nvox, const int32_t* gid, const double* F,
+                               const double* Fp_n, const double* rho_ssd_n,
+                               const double* rho_gnd_n, double dt, double* dg, double* P,
+                               double* K, int32_t* iters, void* stream);
+
+/* Projection G of eq. 17 applied to a real FP64 field A (device, 9 x nvox, grid n) with
+ * the mixed-control zero-frequency rule of mask (host, 9) and target dc_target (host, 9;
+ * NULL = 0); result in out (device, 9 x nvox).  precision selects FP64 or FP32 spectra. */
+int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
+                    const double* dc_target, double* out, void* stream);
+
+/* Nye tensor alpha_ij = eps_jml d_m Fp_il (eq. 12 with the rotated-scheme derivative of
+ * Appendix A and voxel size h; device in/out, 9 x nvox) and, when gid/grain_quat are
+ * given, the GND densities per slip system (eq. 13; device out, 12 x nvox). */
+int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const double* Fp,
+                          double* nye, const int32_t* gid, int32_t n_grains,
+                          const double* grain_quat, double burgers, double* rho_gnd, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_H */

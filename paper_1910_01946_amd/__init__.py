@@ -1,0 +1,152 @@
+"""MI355X (gfx950) FFT strain-gradient crystal-plasticity homogenization.
+
+Python binding of the C library (include/rve.h): argument marshalling only, every step
+of the homogenization runs in the library's HIP kernels.  PyTorch supplies device memory
+and streams for the kernel-level entry points.  There is no CPU fallback: without the
+built library every call raises LibraryMissing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rve_desc, rve_material,
+                   rve_options, rve_step_stats)
+
+__all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
+           "spectral_curl", "LibraryMissing", "RVEError", "lib"]
+
+FIELDS = {"F": (0, 9), "P": (1, 9), "Fp": (2, 9), "rho_ssd": (3, 12), "rho_gnd": (4, 12),
+          "nye": (5, 9), "dg": (6, 12)}
+
+
+def make_material(m) -> rve_material:
+    """rve_material from any object with the synth.Material attributes."""
+    out = rve_material()
+    for k in ("C11", "C12", "C44", "mu", "burgers", "y_c", "K_sim", "gamma0_dot", "m_rate", "tau0",
+              "rho0", "c_gnd"):
+        setattr(out, k, float(getattr(m, k)))
+    for i, v in enumerate(m.q):
+        out.q[i] = float(v)
+    out.hardening = int(m.hardening)
+    return out
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Homogenizer:
+    """A set of RVEs advanced together through rve_step_increment."""
+
+    def __init__(self, rves, precision=RVE_FP64, newton_tol=1e-10, cg_tol=1e-8, max_newton=40,
+                 max_cg=2000, max_backtrack=12, device=0, stream=None):
+        L = lib()
+        n = len(rves)
+        self._keep = []
+        descs = (rve_desc * n)()
+        for i, r in enumerate(rves):
+            gid = np.ascontiguousarray(r.grain_of_voxel.reshape(-1), dtype=np.int32)
+            q = np.ascontiguousarray(r.quats, dtype=np.float64)
+            self._keep += [gid, q]
+            d = descs[i]
+            d.n[0], d.n[1], d.n[2] = (int(v) for v in r.n)
+            d.voxel_size = float(r.voxel_size)
+            d.n_grains = int(q.shape[0])
+            d.grain_of_voxel = gid.ctypes.data_as(C.POINTER(C.c_int32))
+            d.grain_quat = _dp(q)
+            d.material = make_material(r.material)
+        opt = rve_options(precision=precision, newton_tol=newton_tol, cg_tol=cg_tol, max_newton=max_newton,
+                          max_cg=max_cg, max_backtrack=max_backtrack, device=device,
+                          stream=C.c_void_p(stream) if stream else None)
+        h = C.c_void_p()
+        check(L.rve_create(descs, n, C.byref(opt), C.byref(h)))
+        self.h = h
+        self.rves = rves
+        self.n_rve = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, F_bar, mask, P_bar, dt):
+        """One increment for every RVE; F_bar, P_bar: (9,) or (n_rve, 9).  Returns stats dicts."""
+        F = np.ascontiguousarray(np.broadcast_to(np.asarray(F_bar, float).reshape(-1, 9), (self.n_rve, 9)))
+        P = np.ascontiguousarray(np.broadcast_to(np.asarray(P_bar, float).reshape(-1, 9), (self.n_rve, 9)))
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(9))
+        st = (rve_step_stats * self.n_rve)()
+        rc = lib().rve_step_increment(self.h, _dp(F), m.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(P),
+                                      float(dt), st)
+        stats = [s.as_dict() for s in st]
+        if rc != 0:
+            err = RVEError(rc, lib().rve_last_error().decode())
+            err.stats = stats
+            raise err
+        return stats
+
+    def macro(self, i=0):
+        P = np.zeros(9)
+        F = np.zeros(9)
+        s = np.zeros(9)
+        check(lib().rve_macro_stress(self.h, i, _dp(P), _dp(F), _dp(s)))
+        return P, F, s
+
+    def field(self, name, i=0):
+        which, nc = FIELDS[name]
+        out = np.zeros((nc, self.rves[i].n_vox))
+        check(lib().rve_get_field(self.h, i, which, _dp(out)))
+        return out
+
+    def save_state(self):
+        nb = lib().rve_state_bytes(self.h)
+        buf = np.zeros(nb, dtype=np.uint8)
+        check(lib().rve_save_state(self.h, buf.ctypes.data_as(C.c_void_p)))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lib().rve_load_state(self.h, buf.ctypes.data_as(C.c_void_p)))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    return C.c_void_p(stream) if stream else None
+
+
+def constitutive_batch(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, P, K=None, iters=None,
+                       stream=None):
+    """Kernel-level constitutive update on torch device tensors (component-major fields)."""
+    q = np.ascontiguousarray(quats, dtype=np.float64)
+    m = make_material(mat)
+    check(lib().rve_constitutive_batch(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
+                                       _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
+                                       _ptr(dg), _ptr(P), _ptr(K), _ptr(iters), _stream(stream)))
+
+
+def project(n, A, mask, out, dc_target=None, precision=RVE_FP64, stream=None):
+    nn = (C.c_int32 * 3)(*[int(v) for v in n])
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(9))
+    dc = None if dc_target is None else np.ascontiguousarray(np.asarray(dc_target, float).reshape(9))
+    check(lib().rve_project(nn, precision, _ptr(A), m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                            _dp(dc) if dc is not None else None, _ptr(out), _stream(stream)))
+
+
+def spectral_curl(n, h, Fp, nye, gid=None, quats=None, burgers=0.0, rho_gnd=None, precision=RVE_FP64,
+                  stream=None):
+    nn = (C.c_int32 * 3)(*[int(v) for v in n])
+    q = None if quats is None else np.ascontiguousarray(quats, dtype=np.float64)
+    check(lib().rve_spectral_curl(nn, precision, float(h), _ptr(Fp), _ptr(nye), _ptr(gid),
+                                  0 if q is None else int(q.shape[0]), _dp(q) if q is not None else None,
+                                  float(burgers), _ptr(rho_gnd), _stream(stream)))

@@ -1,0 +1,478 @@
+// Constitutive update of the strain-gradient crystal-plasticity model (Section 2.1,
+// eqs. 1-9 and 14), one voxel per lane, FP64.
+//
+// Frames.  A grain with rotation R (crystal -> sample) has slip systems s = R s0,
+// m = R m0 and stiffness C = R*R*C0*R*R.  The update is rotation-equivariant, so it is
+// evaluated in the crystal frame: F_c = R^T F R, Fp_c = R^T Fp R, with the fixed FCC slip
+// systems and the cubic stiffness as compile-time constants, and P = R P_c R^T.  The
+// tangent is stored in the crystal frame: K_c[(3i+j)*9 + (3k+l)] = dP_c,ij / dF_c,kl.
+//
+// Time integration over an increment dt (backward Euler in the slip increments dg):
+//   Fp = A Fp_n,  A = I + sum_a dg_a s_a (x) m_a                        (eq. 2)
+//   Fe = F Fp^{-1},  Ee = (Fe^T Fe - I)/2,  S = C : Ee,  tau_a = S : (s_a (x) m_a)   (1, 3-5)
+//   R_a(dg) = dg_a - dt gdot0 (|tau_a| / tau_c,a)^n sgn(tau_a),  n = 1/m     (eq. 6)
+//   tau_c,a = mu b sqrt(sum_b q_ab (rho_SSD,b + c_gnd rho_GND,b)) from the densities at
+//   the start of the increment (eq. 7); the densities advance after the increment (eq. 8).
+//   P = F Fp^{-1} S Fp^{-T}  (= Fe S Fe^T F^{-T}, eq. 14).
+//
+// Local solve.  Newton on R(dg) = 0 with the analytic Jacobian
+//   J_ab = delta_ab + D_a (u_b . Chat_a w_b),  D_a = d g_a / d tau_a,
+//   u_b = Ce s_b, w_b = A^{-T} m_b, Chat_a = C : sym(s_a (x) m_a),
+// solved by Gaussian elimination without pivoting (J = D (D^{-1} + M) with M close to a
+// symmetric positive semi-definite Gram matrix, so elimination is stable), steps capped
+// at 0.02 in the max norm and backtracked on |R|.  If 8 Newton steps at the final
+// exponent do not converge from the warm start, the lane restarts with continuation in
+// the exponent (roots at n = 1, 2, 4, 8, 16, then n = 1/m): far from the solution the
+// Jacobian rows of overloaded systems carry (|tau|/tau_c)^(n-1) and J becomes
+// numerically singular; each continuation stage starts close to its own root.
+//
+// Tangent.  With the converged J (plain rows), for each unit direction dF = e_k (x) e_l:
+//   dtau_a = Fe_k. Chat_a G_l.  (G = Fp^{-1}),  ddg = J^{-1} (D dtau),  Z = sum_b ddg_b s_b (x) m_b,
+//   dEe = sym(Fe_k. (x) G_l.) - sym(Ce Z A^{-1}),  dS = C : dEe,
+//   dP = e_k (x) (G S G^T)_l. - Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T.
+#include "common.h"
+#include "kernels.h"
+
+namespace rve {
+
+namespace {
+
+__device__ __forceinline__ double ipow(double r, int k) {
+  double res = 1.0, b = r;
+  while (k) {
+    if (k & 1) res *= b;
+    b *= b;
+    k >>= 1;
+  }
+  return res;
+}
+
+__device__ __forceinline__ double powr(double r, double n) {
+  if (r == 0.0) return n == 0.0 ? 1.0 : 0.0;
+  if (n == floor(n) && n >= 0.0 && n <= 64.0) return ipow(r, (int)n);
+  return pow(r, n);
+}
+
+struct Point {
+  double Fe0[9];   // F_c Fp_n,c^{-1}
+  double Gn[9];    // Fp_n,c^{-1}
+  double tc[12];
+  double a;        // dt * gdot0
+  double C11, C12, C44;
+};
+
+__device__ __forceinline__ void cubic_stress(const Point& p, const double* E, double* S) {
+  const double tr = E[0] + E[4] + E[8];
+  const double d = p.C11 - p.C12;
+  S[0] = p.C12 * tr + d * E[0];
+  S[4] = p.C12 * tr + d * E[4];
+  S[8] = p.C12 * tr + d * E[8];
+  S[1] = S[3] = 2.0 * p.C44 * E[1];
+  S[2] = S[6] = 2.0 * p.C44 * E[2];
+  S[5] = S[7] = 2.0 * p.C44 * E[5];
+}
+
+// u^T Chat_a w for the cubic stiffness: Chat_a = 2 C44 sym(s m) + (C11-C12-2C44) diag(s_i m_i)
+__device__ __forceinline__ double uCw(const Point& p, int a, const double* u, const double* w) {
+  const double us = u[0] * kSlipS[a][0] + u[1] * kSlipS[a][1] + u[2] * kSlipS[a][2];
+  const double um = u[0] * kSlipM[a][0] + u[1] * kSlipM[a][1] + u[2] * kSlipM[a][2];
+  const double ws = w[0] * kSlipS[a][0] + w[1] * kSlipS[a][1] + w[2] * kSlipS[a][2];
+  const double wm = w[0] * kSlipM[a][0] + w[1] * kSlipM[a][1] + w[2] * kSlipM[a][2];
+  const double dd = u[0] * w[0] * kSlipS[a][0] * kSlipM[a][0] + u[1] * w[1] * kSlipS[a][1] * kSlipM[a][1] +
+                    u[2] * w[2] * kSlipS[a][2] * kSlipM[a][2];
+  return p.C44 * (us * wm + um * ws) + (p.C11 - p.C12 - 2.0 * p.C44) * dd;
+}
+
+struct Kin {
+  double A[9], Ainv[9], Fe[9], Ce[9], S[9], tau[12];
+};
+
+__device__ __forceinline__ void kinematics(const Point& p, const double* dg, Kin& k) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) k.A[i] = (i % 4 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) k.A[3 * i + j] += dg[a] * kSlipS[a][i] * kSlipM[a][j];
+  inv3(k.A, k.Ainv);
+  mm3(p.Fe0, k.Ainv, k.Fe);
+  mtm3(k.Fe, k.Fe, k.Ce);
+  double E[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) E[i] = 0.5 * (k.Ce[i] - ((i % 4 == 0) ? 1.0 : 0.0));
+  cubic_stress(p, E, k.S);
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t += kSlipS[a][i] * k.S[3 * i + j] * kSlipM[a][j];
+    k.tau[a] = t;
+  }
+}
+
+// R = dg - g(tau); returns |R|^2.  D (may be null) receives d g_a / d tau_a.
+__device__ __forceinline__ double residual(const Point& p, double n, const double* dg, Kin& k, double* R,
+                                           double* D) {
+  kinematics(p, dg, k);
+  double r2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const double ratio = fabs(k.tau[a]) / p.tc[a];
+    const double rn1 = powr(ratio, n - 1.0);
+    const double g = p.a * rn1 * ratio * ((k.tau[a] > 0.0) ? 1.0 : ((k.tau[a] < 0.0) ? -1.0 : 0.0));
+    R[a] = dg[a] - g;
+    r2 += R[a] * R[a];
+    if (D) D[a] = p.a * n * rn1 / p.tc[a];
+  }
+  return r2;
+}
+
+__device__ __forceinline__ void jacobian(const Point& p, const Kin& k, const double* D, double J[12][12]) {
+#pragma unroll
+  for (int b = 0; b < 12; ++b) {
+    double u[3], w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[i] = k.Ce[3 * i] * kSlipS[b][0] + k.Ce[3 * i + 1] * kSlipS[b][1] + k.Ce[3 * i + 2] * kSlipS[b][2];
+      w[i] = k.Ainv[i] * kSlipM[b][0] + k.Ainv[3 + i] * kSlipM[b][1] + k.Ainv[6 + i] * kSlipM[b][2];
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) J[a][b] = ((a == b) ? 1.0 : 0.0) + D[a] * uCw(p, a, u, w);
+  }
+}
+
+__device__ __forceinline__ void lu12(double J[12][12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double ip = 1.0 / J[c][c];
+#pragma unroll
+    for (int r = c + 1; r < 12; ++r) {
+      const double f = J[r][c] * ip;
+      J[r][c] = f;
+#pragma unroll
+      for (int cc = c + 1; cc < 12; ++cc) J[r][cc] -= f * J[c][cc];
+    }
+  }
+}
+
+__device__ __forceinline__ void lu12_solve(const double J[12][12], double* x) {
+#pragma unroll
+  for (int r = 1; r < 12; ++r)
+#pragma unroll
+    for (int c = 0; c < r; ++c) x[r] -= J[r][c] * x[c];
+#pragma unroll
+  for (int r = 11; r >= 0; --r) {
+#pragma unroll
+    for (int c = r + 1; c < 12; ++c) x[r] -= J[r][c] * x[c];
+    x[r] /= J[r][r];
+  }
+}
+
+// Newton iterations at exponent n; returns 1 if converged.  iters accumulates.
+__device__ int newton(const Point& p, double n, double tol, int maxit, double* dg, int& iters) {
+  const double floor_ = 1e-10, max_step = 0.02;
+  Kin k;
+  double R[12], D[12], J[12][12], d[12];
+  for (int it = 0; it < maxit; ++it) {
+    const double r2 = residual(p, n, dg, k, R, D);
+    jacobian(p, k, D, J);
+    lu12(J);
+#pragma unroll
+    for (int a = 0; a < 12; ++a) d[a] = -R[a];
+    lu12_solve(J, d);
+    ++iters;
+    double big = 0.0, xmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      big = fmax(big, fabs(d[a]));
+      xmax = fmax(xmax, fabs(dg[a]));
+    }
+    if (!(big < 1e300)) return 0;  // non-finite step
+    if (big > max_step) {
+      const double s = max_step / big;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) d[a] *= s;
+      big = max_step;
+    }
+    if (big <= tol * fmax(xmax, floor_)) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) dg[a] += d[a];
+      return 1;
+    }
+    double lam = 1.0, trial[12];
+    for (int ls = 0; ls < 30; ++ls) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) trial[a] = dg[a] + lam * d[a];
+      const double rt = residual(p, n, trial, k, R, nullptr);
+      if (rt <= r2) break;
+      lam *= 0.5;
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) dg[a] = trial[a];
+  }
+  return 0;
+}
+
+}  // namespace
+
+template <typename KT>
+__global__ void __launch_bounds__(64) k_constitutive(ConstArgs args) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = args.nvox;
+  __shared__ int s_it[64];
+  __shared__ int s_fail[64];
+  int my_it = 0, my_fail = 0;
+  if (v < nv) {
+    const MatDev& M = *args.mat;
+    const int g = args.gid[v];
+    double Rg[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rg[i] = args.grainR[9 * g + i];
+    double Fs[9], Fps[9], Fc[9], Fpc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double f = args.F[i * nv + v];
+      if (args.dF) f += args.lam * (double)reinterpret_cast<const KT*>(args.dF)[i * nv + v];
+      Fs[i] = f;
+      Fps[i] = args.Fp_n[i * nv + v];
+    }
+    if (args.F_out) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) args.F_out[i * nv + v] = Fs[i];
+    }
+    to_crystal(Rg, Fs, Fc);
+    to_crystal(Rg, Fps, Fpc);
+    Point p;
+    p.C11 = M.C11;
+    p.C12 = M.C12;
+    p.C44 = M.C44;
+    p.a = args.dt * M.gamma0_dot;
+    inv3(Fpc, p.Gn);
+    mm3(Fc, p.Gn, p.Fe0);
+    if (M.hardening) {
+      double forest[12];
+#pragma unroll
+      for (int b = 0; b < 12; ++b) forest[b] = args.rho_ssd[b * nv + v] + M.c_gnd * args.rho_gnd[b * nv + v];
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) s += M.q[12 * a + b] * forest[b];
+        p.tc[a] = M.mu * M.burgers * sqrt(s);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) p.tc[a] = M.tau_c_frozen;
+    }
+    double dg0[12], dg[12];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) dg0[a] = dg[a] = args.dg[a * nv + v];
+    const double n_final = M.n_exp;
+    int it = 0;
+    int ok = newton(p, n_final, 1e-10, 8, dg, it);
+    if (!ok) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) dg[a] = dg0[a];
+      const double stages[5] = {1.0, 2.0, 4.0, 8.0, 16.0};
+      for (int s = 0; s < 5; ++s) {
+        if (stages[s] >= n_final) break;
+        newton(p, stages[s], 1e-4, 60, dg, it);
+      }
+      ok = newton(p, n_final, 1e-10, 60, dg, it);
+    }
+    my_it = it;
+    my_fail = ok ? 0 : 1;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) args.dg[a * nv + v] = dg[a];
+    // stress at the converged slip increments
+    Kin k;
+    double R[12], D[12];
+    residual(p, n_final, dg, k, R, D);
+    double G[9], Gt_tmp[9], SGt[9], Pc[9], Ps[9];
+    mm3(p.Gn, k.Ainv, G);            // Fp^{-1}
+    mmt3(k.S, G, SGt);               // S G^T
+    mm3(k.Fe, SGt, Pc);              // P_c = Fe S G^T
+    to_sample(Rg, Pc, Ps);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) args.P[i * nv + v] = ok ? Ps[i] : NAN;
+    (void)Gt_tmp;
+    if (args.K && ok) {
+      double J[12][12];
+      jacobian(p, k, D, J);
+      lu12(J);
+      double H[9], Q[9], W[9], AtS[9];
+      mm3(G, SGt, H);                // G S G^T
+      mm3(k.Ainv, SGt, Q);           // A^{-1} S G^T
+      mmt3(k.S, k.Ainv, AtS);        // S A^{-T}
+      mm3(k.Fe, AtS, W);             // Fe S A^{-T}
+      KT* Kout = reinterpret_cast<KT*>(args.K);
+#pragma unroll 1
+      for (int kk = 0; kk < 3; ++kk) {
+#pragma unroll 1
+        for (int ll = 0; ll < 3; ++ll) {
+          const double av[3] = {k.Fe[3 * kk], k.Fe[3 * kk + 1], k.Fe[3 * kk + 2]};
+          const double bv[3] = {G[3 * ll], G[3 * ll + 1], G[3 * ll + 2]};
+          double x[12];
+#pragma unroll
+          for (int a = 0; a < 12; ++a) x[a] = D[a] * uCw(p, a, av, bv);
+          lu12_solve(J, x);
+          double Z[9];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              double z = 0.0;
+#pragma unroll
+              for (int b = 0; b < 12; ++b) z += x[b] * kSlipS[b][i] * kSlipM[b][j];
+              Z[3 * i + j] = z;
+            }
+          double CeZ[9], CeZA[9], dE[9], dS[9];
+          mm3(k.Ce, Z, CeZ);
+          mm3(CeZ, k.Ainv, CeZA);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              dE[3 * i + j] = 0.5 * (av[i] * bv[j] + av[j] * bv[i]) - 0.5 * (CeZA[3 * i + j] + CeZA[3 * j + i]);
+          cubic_stress(p, dE, dS);
+          double t1[9], t2[9], dP[9];
+          // - Fe Z Q
+          mm3(Z, Q, t1);
+          mm3(k.Fe, t1, dP);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) dP[i] = -dP[i];
+          // + Fe dS G^T
+          mmt3(dS, G, t1);
+          mm3(k.Fe, t1, t2);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) dP[i] += t2[i];
+          // - W Z^T G^T = - W (G Z)^T
+          mm3(G, Z, t1);
+          mmt3(W, t1, t2);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
+          // + e_k (x) H_l.
+#pragma unroll
+          for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];
+          const int col = 3 * kk + ll;
+#pragma unroll
+          for (int r = 0; r < 9; ++r) Kout[(int64_t)(r * 9 + col) * nv + v] = (KT)dP[r];
+        }
+      }
+    }
+  }
+  if (args.blk_stats) {
+    s_it[threadIdx.x] = my_it;
+    s_fail[threadIdx.x] = my_fail;
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        s_it[threadIdx.x] = max(s_it[threadIdx.x], s_it[threadIdx.x + s]);
+        s_fail[threadIdx.x] += s_fail[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      args.blk_stats[2 * blockIdx.x] = s_it[0];
+      args.blk_stats[2 * blockIdx.x + 1] = s_fail[0];
+    }
+  }
+  if (args.iters && v < nv) args.iters[v] = my_fail ? -my_it - 1 : my_it;
+}
+
+// Commit of an increment: Fp = (R A_c R^T) Fp_n and rho_SSD = rho_SSD,n + h |dg| (eq. 8),
+// h = (1/b)(1/l - 2 y_c rho_SSD,n), l = K / sqrt(sum_{b != a} (rho_SSD,n + c_gnd rho_GND,n)).
+__global__ void k_commit(CommitArgs args) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = args.nvox;
+  if (v >= nv) return;
+  const MatDev& M = *args.mat;
+  const int g = args.gid[v];
+  double Rg[9], dg[12], Ac[9], As[9], Fpn[9], Fp[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rg[i] = args.grainR[9 * g + i];
+#pragma unroll
+  for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Ac[i] = (i % 4 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ac[3 * i + j] += dg[a] * kSlipS[a][i] * kSlipM[a][j];
+  to_sample(Rg, Ac, As);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fpn[i] = args.Fp[i * nv + v];
+  mm3(As, Fpn, Fp);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) args.Fp[i * nv + v] = Fp[i];
+  if (M.hardening) {
+    double rs[12], forest[12], tot = 0.0;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      rs[a] = args.rho_ssd[a * nv + v];
+      forest[a] = rs[a] + M.c_gnd * args.rho_gnd[a * nv + v];
+      tot += forest[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      const double ell = M.K_sim / sqrt(tot - forest[a]);
+      const double h = (1.0 / M.burgers) * (1.0 / ell - 2.0 * M.y_c * rs[a]);
+      args.rho_ssd[a * nv + v] = rs[a] + h * fabs(dg[a]);
+    }
+  }
+}
+
+// Rotate crystal-frame tangents to the sample frame (kernel-level test entry point).
+__global__ void k_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc,
+                                 double* Ks) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const int g = gid[v];
+  double Rg[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rg[i] = grainR[9 * g + i];
+  double T[81];
+  // T[pq][kl] = sum_rs Kc[pq][rs] R_kr R_ls
+  for (int pq = 0; pq < 9; ++pq) {
+    double X[9], Y[9];
+    for (int rs = 0; rs < 9; ++rs) X[rs] = Kc[(int64_t)(pq * 9 + rs) * nv + v];
+    to_sample(Rg, X, Y);
+    for (int kl = 0; kl < 9; ++kl) T[pq * 9 + kl] = Y[kl];
+  }
+  for (int kl = 0; kl < 9; ++kl) {
+    double X[9], Y[9];
+    for (int pq = 0; pq < 9; ++pq) X[pq] = T[pq * 9 + kl];
+    to_sample(Rg, X, Y);
+    for (int ij = 0; ij < 9; ++ij) Ks[(int64_t)(ij * 9 + kl) * nv + v] = Y[ij];
+  }
+}
+
+void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st) {
+  const int bs = 64;
+  const int64_t nb = (a.nvox + bs - 1) / bs;
+  if (fp32_tangent)
+    hipLaunchKernelGGL(k_constitutive<float>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_constitutive<double>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+}
+
+void launch_commit(const CommitArgs& a, hipStream_t st) {
+  const int bs = 256;
+  const int64_t nb = (a.nvox + bs - 1) / bs;
+  hipLaunchKernelGGL(k_commit, dim3((unsigned)nb), dim3(bs), 0, st, a);
+}
+
+void launch_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc, double* Ks,
+                           hipStream_t st) {
+  const int bs = 128;
+  const int64_t nb = (nv + bs - 1) / bs;
+  hipLaunchKernelGGL(k_rotate_tangent, dim3((unsigned)nb), dim3(bs), 0, st, nv, gid, grainR, Kc, Ks);
+}
+
+}  // namespace rve

@@ -1,0 +1,57 @@
+// Kernel argument structures and launchers shared by the kernel files and the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rve {
+
+// Material constants of one RVE, device resident (read through the scalar cache).
+struct MatDev {
+  double C11, C12, C44;
+  double mu, burgers, y_c, K_sim;
+  double gamma0_dot, n_exp;      // n_exp = 1 / m
+  double c_gnd, tau_c_frozen;
+  int32_t hardening, pad;
+  double q[144];                 // interaction matrix, row-major
+  double Aplus[18 * 9];          // minimum-norm inverse of the segment matrix (eq. 13)
+  int32_t screw_of[12];          // screw segment sharing the Burgers vector of each system
+};
+
+struct ConstArgs {
+  int64_t nvox;
+  const int32_t* gid;
+  const double* grainR;          // 9 per grain, crystal -> sample
+  const MatDev* mat;
+  const double* F;               // evaluated at F + lam * dF (dF may be null)
+  const void* dF;                // same type as the tangent (double or float)
+  double lam;
+  double* F_out;                 // optional copy of the evaluated F
+  const double* Fp_n;
+  const double* rho_ssd;
+  const double* rho_gnd;
+  double* dg;                    // in: warm start, out: converged slip increments
+  double* P;
+  void* K;                       // crystal-frame tangent (double or float), may be null
+  double dt;
+  int32_t* blk_stats;            // per block {max local iterations, failures}, may be null
+  int32_t* iters;                // per voxel local iterations (negative: failed), may be null
+};
+
+struct CommitArgs {
+  int64_t nvox;
+  const int32_t* gid;
+  const double* grainR;
+  const MatDev* mat;
+  const double* dg;
+  double* Fp;                    // in: Fp_n, out: Fp
+  double* rho_ssd;               // in: rho_SSD,n, out: rho_SSD
+  const double* rho_gnd;
+};
+
+void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st);
+void launch_commit(const CommitArgs& a, hipStream_t st);
+void launch_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc, double* Ks,
+                           hipStream_t st);
+
+}  // namespace rve

@@ -1,0 +1,1060 @@
+// Host runtime of the library: RVE set-up, the Newton / conjugate-gradient increment
+// loop of Section 2.2 (eqs. 15-18), commit, Nye tensor and GND densities, and the C ABI
+// declared in include/rve.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "kernels.h"
+#include "spectral.h"
+
+namespace rve {
+
+// ------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  int32_t code;
+  Error(int32_t c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(x)                                                                                  \
+  do {                                                                                               \
+    hipError_t e_ = (x);                                                                             \
+    if (e_ != hipSuccess)                                                                            \
+      throw Error(e_ == hipErrorOutOfMemory ? RVE_ENOMEM : RVE_EDEVICE,                              \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                                   \
+  } while (0)
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(RVE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------------------------
+// host-side tables (independent of any other implementation)
+// ------------------------------------------------------------------------------------
+static const int kPlane[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+static const int kDir[12][3] = {{0, 1, -1}, {-1, 0, 1}, {1, -1, 0}, {0, 1, -1}, {1, 0, 1}, {1, 1, 0},
+                                {0, 1, 1},  {1, 0, -1}, {1, 1, 0},  {0, 1, 1},  {1, 0, 1}, {1, -1, 0}};
+
+static int dot3i(const int* a, const int* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// q^{ab} from the six Table 1 coefficients (self, coplanar, collinear, Hirth, glissile, Lomer)
+static void interaction_matrix(const double* coef, double* q) {
+  for (int a = 0; a < 12; ++a)
+    for (int b = 0; b < 12; ++b) {
+      const int* na = kPlane[a / 3];
+      const int* nb = kPlane[b / 3];
+      const int* sa = kDir[a];
+      const int* sb = kDir[b];
+      int cls;
+      if (a == b) cls = 0;
+      else if (a / 3 == b / 3) cls = 1;
+      else {
+        const int cx = sa[1] * sb[2] - sa[2] * sb[1], cy = sa[2] * sb[0] - sa[0] * sb[2],
+                  cz = sa[0] * sb[1] - sa[1] * sb[0];
+        if (cx == 0 && cy == 0 && cz == 0) cls = 2;
+        else if (dot3i(sa, sb) == 0) cls = 3;
+        else {
+          int j[3];
+          for (int i = 0; i < 3; ++i) j[i] = sa[i] + sb[i];
+          if (dot3i(j, j) != 2)
+            for (int i = 0; i < 3; ++i) j[i] = sa[i] - sb[i];
+          cls = (dot3i(j, na) == 0 || dot3i(j, nb) == 0) ? 4 : 5;
+        }
+      }
+      q[12 * a + b] = coef[cls];
+    }
+}
+
+// A (9 x 18): edge columns vec(b (x) t), t = m x b; screw columns vec(b (x) b); A^+ = A^T (A A^T)^{-1}
+static void segment_pinv(double* Aplus, int* screw_of) {
+  double A[9][18];
+  double sdir[6][3];
+  int nscrew = 0;
+  for (int a = 0; a < 12; ++a) {
+    double b[3], m[3], t[3];
+    const double ib = 1.0 / std::sqrt(2.0), im = 1.0 / std::sqrt(3.0);
+    for (int i = 0; i < 3; ++i) {
+      b[i] = kDir[a][i] * ib;
+      m[i] = kPlane[a / 3][i] * im;
+    }
+    t[0] = m[1] * b[2] - m[2] * b[1];
+    t[1] = m[2] * b[0] - m[0] * b[2];
+    t[2] = m[0] * b[1] - m[1] * b[0];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[3 * i + j][a] = b[i] * t[j];
+    int found = -1;
+    for (int s = 0; s < nscrew; ++s) {
+      const double d = std::fabs(sdir[s][0] * b[0] + sdir[s][1] * b[1] + sdir[s][2] * b[2]);
+      if (std::fabs(d - 1.0) < 1e-12) found = s;
+    }
+    if (found < 0) {
+      for (int i = 0; i < 3; ++i) sdir[nscrew][i] = b[i];
+      found = nscrew++;
+    }
+    screw_of[a] = found;
+  }
+  for (int s = 0; s < 6; ++s)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[3 * i + j][12 + s] = sdir[s][i] * sdir[s][j];
+  // M = A A^T, invert by Gauss-Jordan with partial pivoting
+  double M[9][18];
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 18; ++k) s += A[i][k] * A[j][k];
+      M[i][j] = s;
+      M[i][9 + j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < 9; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 9; ++r)
+      if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+    for (int k = 0; k < 18; ++k) std::swap(M[c][k], M[piv][k]);
+    const double ip = 1.0 / M[c][c];
+    for (int k = 0; k < 18; ++k) M[c][k] *= ip;
+    for (int r = 0; r < 9; ++r)
+      if (r != c) {
+        const double f = M[r][c];
+        for (int k = 0; k < 18; ++k) M[r][k] -= f * M[c][k];
+      }
+  }
+  // A^+ (18 x 9) = A^T M^{-1}
+  for (int s = 0; s < 18; ++s)
+    for (int c = 0; c < 9; ++c) {
+      double v = 0.0;
+      for (int k = 0; k < 9; ++k) v += A[k][s] * M[k][9 + c];
+      Aplus[s * 9 + c] = v;
+    }
+}
+
+static void quat_to_R(const double* q_in, double* R) {
+  double w = q_in[0], x = q_in[1], y = q_in[2], z = q_in[3];
+  const double n = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static MatDev make_material(const rve_material& m) {
+  auto finite_pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+  if (!finite_pos(m.C11) || !finite_pos(m.C44) || !std::isfinite(m.C12) || m.C11 - m.C12 <= 0.0 ||
+      m.C11 + 2 * m.C12 <= 0.0)
+    throw Error(RVE_EINVAL, "elastic constants are not positive definite");
+  if (!finite_pos(m.burgers) || !finite_pos(m.gamma0_dot) || !finite_pos(m.m_rate) || !finite_pos(m.K_sim) ||
+      !(std::isfinite(m.y_c) && m.y_c >= 0.0) || !(std::isfinite(m.c_gnd) && m.c_gnd >= 0.0))
+    throw Error(RVE_EINVAL, "dislocation or flow-rule parameter not positive");
+  MatDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.C11 = m.C11;
+  d.C12 = m.C12;
+  d.C44 = m.C44;
+  d.mu = m.mu > 0 ? m.mu : 3.0 * m.C44 * (m.C11 - m.C12) / (m.C11 - m.C12 + 4.0 * m.C44);
+  d.burgers = m.burgers;
+  d.y_c = m.y_c;
+  d.K_sim = m.K_sim;
+  d.gamma0_dot = m.gamma0_dot;
+  d.n_exp = 1.0 / m.m_rate;
+  d.c_gnd = m.c_gnd;
+  d.hardening = m.hardening ? 1 : 0;
+  interaction_matrix(m.q, d.q);
+  double rowsum = 0.0;
+  for (int b = 0; b < 12; ++b) rowsum += d.q[b];
+  double rho0 = m.rho0;
+  if (!(rho0 > 0.0)) {
+    if (!finite_pos(m.tau0)) throw Error(RVE_EINVAL, "need tau0 > 0 or rho0 > 0");
+    rho0 = std::pow(m.tau0 / (d.mu * d.burgers), 2) / rowsum;
+  }
+  if (!std::isfinite(rho0) || rho0 <= 0.0) throw Error(RVE_EINVAL, "initial density must be positive");
+  d.tau_c_frozen = d.mu * d.burgers * std::sqrt(rowsum * rho0);
+  d.pad = 0;
+  segment_pinv(d.Aplus, d.screw_of);
+  // keep rho0 for the state initialisation in an unused slot
+  return d;
+}
+
+static double initial_rho0(const rve_material& m, const MatDev& d) {
+  if (m.rho0 > 0.0) return m.rho0;
+  double rowsum = 0.0;
+  for (int b = 0; b < 12; ++b) rowsum += d.q[b];
+  return std::pow(m.tau0 / (d.mu * d.burgers), 2) / rowsum;
+}
+
+// ------------------------------------------------------------------------------------
+// grid plans
+// ------------------------------------------------------------------------------------
+static AxisPlan make_axis(int n) {
+  AxisPlan a;
+  a.n = n;
+  a.nrad = 0;
+  int m = n;
+  const int order[5] = {8, 4, 2, 3, 5};
+  for (int r : order)
+    while (m % r == 0 && m > 1) {
+      if (a.nrad >= 8) throw Error(RVE_EINVAL, "grid size has too many factors");
+      a.rad[a.nrad++] = r;
+      m /= r;
+    }
+  if (m != 1) throw Error(RVE_EINVAL, "grid sizes must have prime factors 2, 3 and 5 only");
+  return a;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+    bytes = b;
+    if (b) HIPCHECK(hipMalloc(&p, b));
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct Plan {
+  GridPlan g;
+  DevBuf tw[3], E[3];
+};
+
+static void build_plan(Plan& P, const int n[3], bool fp32) {
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1 || n[d] > 256) throw Error(RVE_EINVAL, "grid sizes must lie in 1..256");
+  GridPlan& g = P.g;
+  g.nx = n[0];
+  g.ny = n[1];
+  g.nz = n[2];
+  g.nxh = n[0] / 2 + 1;
+  g.nvox = (int64_t)n[0] * n[1] * n[2];
+  g.nspec = (int64_t)g.nxh * n[1] * n[2];
+  g.ax = make_axis(n[0]);
+  g.ay = make_axis(n[1]);
+  g.az = make_axis(n[2]);
+  // rows per x block: even, ly * nx <= max(256, 2 nx)
+  int ly = std::max(2, (std::max(256, 2 * g.nx) / g.nx) & ~1);
+  const int ny_even = (g.ny + 1) & ~1;
+  g.ly = std::min(ly, ny_even);
+  g.ty = std::min(16, g.nxh);
+  if (g.ny * g.ty > 16 * 256) g.ty = (16 * 256) / g.ny;
+  g.tz = std::max(1, std::min(g.nxh, (18 * 256) / (9 * g.nz)));
+  // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
+  for (int d = 0; d < 3; ++d) {
+    const int m = n[d];
+    std::vector<double> tw(2 * m), E(2 * m);
+    for (int k = 0; k < m; ++k) {
+      const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)m;
+      double c = (double)cosl(ang), s = (double)sinl(ang);
+      if (k == 0) { c = 1; s = 0; }
+      if (2 * k == m) { c = -1; s = 0; }
+      if (4 * k == m) { c = 0; s = 1; }
+      if (4 * k == 3 * m) { c = 0; s = -1; }
+      tw[2 * k] = c;
+      tw[2 * k + 1] = -s;
+      E[2 * k] = c;
+      E[2 * k + 1] = s;
+    }
+    if (fp32) {
+      std::vector<float> twf(2 * m);
+      for (int i = 0; i < 2 * m; ++i) twf[i] = (float)tw[i];
+      P.tw[d].alloc(sizeof(float) * 2 * m);
+      HIPCHECK(hipMemcpy(P.tw[d].p, twf.data(), sizeof(float) * 2 * m, hipMemcpyHostToDevice));
+    } else {
+      P.tw[d].alloc(sizeof(double) * 2 * m);
+      HIPCHECK(hipMemcpy(P.tw[d].p, tw.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice));
+    }
+    P.E[d].alloc(sizeof(double) * 2 * m);
+    HIPCHECK(hipMemcpy(P.E[d].p, E.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice));
+  }
+  g.twx = P.tw[0].p;
+  g.twy = P.tw[1].p;
+  g.twz = P.tw[2].p;
+  g.Ex = P.E[0].p;
+  g.Ey = P.E[1].p;
+  g.Ez = P.E[2].p;
+}
+
+static size_t tsize(bool fp32) { return fp32 ? 4 : 8; }
+
+// ------------------------------------------------------------------------------------
+// one RVE on the device
+// ------------------------------------------------------------------------------------
+struct RVE {
+  Plan plan;
+  int n[3];
+  int64_t nvox = 0;
+  double h = 0;
+  int n_grains = 0;
+  MatDev mat;
+  double rho0 = 0;
+  DevBuf d_mat, d_gid, d_R;
+  // committed state
+  DevBuf F, F_prev, Fp, rho_ssd, rho_gnd, nye, dg, P;
+  // work
+  DevBuf F_work, F_try, P_work, dg_saved, K, xa, xb, r, p, spec, cg, partial, blk;
+  bool have_prev = false;
+  double Favg[9], Favg_prev[9], Pavg[9];
+  double Fbar_prev[9];
+  int64_t increments = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  bool fp32 = false;
+  rve_options opt;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<std::unique_ptr<RVE>> rves;
+  CGState* host_cg = nullptr;  // pinned
+};
+
+static void upload(DevBuf& b, const void* src, size_t bytes) {
+  b.alloc(bytes);
+  HIPCHECK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+}
+
+static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
+  for (int i = 0; i < 3; ++i) R.n[i] = d.n[i];
+  build_plan(R.plan, d.n, C.fp32);
+  R.nvox = R.plan.g.nvox;
+  if (!(std::isfinite(d.voxel_size) && d.voxel_size > 0)) throw Error(RVE_EINVAL, "voxel_size must be > 0");
+  R.h = d.voxel_size;
+  if (d.n_grains < 1 || !d.grain_of_voxel || !d.grain_quat) throw Error(RVE_EINVAL, "missing grain data");
+  R.n_grains = d.n_grains;
+  for (int64_t v = 0; v < R.nvox; ++v)
+    if (d.grain_of_voxel[v] < 0 || d.grain_of_voxel[v] >= d.n_grains)
+      throw Error(RVE_EINVAL, "grain id out of range at voxel " + std::to_string(v));
+  std::vector<double> Rg(9 * (size_t)d.n_grains);
+  for (int gi = 0; gi < d.n_grains; ++gi) {
+    const double* q = d.grain_quat + 4 * gi;
+    const double nn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    if (!(std::isfinite(nn) && nn > 0)) throw Error(RVE_EINVAL, "bad quaternion");
+    quat_to_R(q, &Rg[9 * gi]);
+  }
+  R.mat = make_material(d.material);
+  R.rho0 = initial_rho0(d.material, R.mat);
+  upload(R.d_mat, &R.mat, sizeof(MatDev));
+  upload(R.d_gid, d.grain_of_voxel, sizeof(int32_t) * R.nvox);
+  upload(R.d_R, Rg.data(), sizeof(double) * Rg.size());
+  const int64_t nv = R.nvox;
+  const size_t f9 = sizeof(double) * 9 * nv, f12 = sizeof(double) * 12 * nv;
+  std::vector<double> eye(9 * nv, 0.0), rho(12 * nv, R.rho0);
+  for (int c = 0; c < 9; c += 4)
+    for (int64_t v = 0; v < nv; ++v) eye[c * nv + v] = 1.0;
+  upload(R.F, eye.data(), f9);
+  upload(R.F_prev, eye.data(), f9);
+  upload(R.Fp, eye.data(), f9);
+  upload(R.rho_ssd, rho.data(), f12);
+  R.rho_gnd.alloc(f12);
+  HIPCHECK(hipMemset(R.rho_gnd.p, 0, f12));
+  R.nye.alloc(f9);
+  HIPCHECK(hipMemset(R.nye.p, 0, f9));
+  R.dg.alloc(f12);
+  HIPCHECK(hipMemset(R.dg.p, 0, f12));
+  R.P.alloc(f9);
+  HIPCHECK(hipMemset(R.P.p, 0, f9));
+  R.F_work.alloc(f9);
+  R.F_try.alloc(f9);
+  R.P_work.alloc(f9);
+  R.dg_saved.alloc(f12);
+  const size_t ts = tsize(C.fp32);
+  R.K.alloc(ts * 81 * nv);
+  R.xa.alloc(ts * 9 * nv);
+  R.xb.alloc(ts * 9 * nv);
+  R.r.alloc(ts * 9 * nv);
+  R.p.alloc(ts * 9 * nv);
+  R.spec.alloc(ts * 2 * 9 * R.plan.g.nspec);
+  R.cg.alloc(sizeof(CGState));
+  HIPCHECK(hipMemset(R.cg.p, 0, sizeof(CGState)));
+  const int nb = std::max(xfwd_blocks(R.plan.g), 1024);
+  R.partial.alloc(sizeof(double) * 12 * nb);
+  R.blk.alloc(sizeof(int32_t) * 2 * ((nv + 63) / 64));
+  for (int i = 0; i < 9; ++i) {
+    R.Favg[i] = R.Favg_prev[i] = R.Fbar_prev[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    R.Pavg[i] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// building blocks of an increment
+// ------------------------------------------------------------------------------------
+struct LocalStats {
+  int max_iters = 0;
+  int failures = 0;
+};
+
+static LocalStats run_constitutive(Ctx& C, RVE& R, const double* F, const void* dF, double lam, double* F_out,
+                                   double dt, bool tangent) {
+  ConstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nvox = R.nvox;
+  a.gid = R.d_gid.as<int32_t>();
+  a.grainR = R.d_R.as<double>();
+  a.mat = R.d_mat.as<MatDev>();
+  a.F = F;
+  a.dF = dF;
+  a.lam = lam;
+  a.F_out = F_out;
+  a.Fp_n = R.Fp.as<double>();
+  a.rho_ssd = R.rho_ssd.as<double>();
+  a.rho_gnd = R.rho_gnd.as<double>();
+  a.dg = R.dg.as<double>();
+  a.P = R.P_work.as<double>();
+  a.K = tangent ? R.K.p : nullptr;
+  a.dt = dt;
+  a.blk_stats = R.blk.as<int32_t>();
+  launch_constitutive(a, C.fp32, C.stream);
+  check_launch("constitutive");
+  const int64_t nb = (R.nvox + 63) / 64;
+  std::vector<int32_t> st(2 * nb);
+  HIPCHECK(hipMemcpyAsync(st.data(), R.blk.p, sizeof(int32_t) * 2 * nb, hipMemcpyDeviceToHost, C.stream));
+  HIPCHECK(hipStreamSynchronize(C.stream));
+  LocalStats ls;
+  for (int64_t b = 0; b < nb; ++b) {
+    ls.max_iters = std::max(ls.max_iters, st[2 * b]);
+    ls.failures += st[2 * b + 1];
+  }
+  return ls;
+}
+
+// projected apply of a stress-like FP64 field: r = -G(P - Pbar), p = r, x = 0; returns r.r
+static double run_residual(Ctx& C, RVE& R, const double* P64, const double* mask_keep, const double* target,
+                           void* x_zero) {
+  const GridPlan& g = R.plan.g;
+  XFwdArgs xf;
+  std::memset(&xf, 0, sizeof(xf));
+  xf.mode = XF_FIELD64;
+  xf.in64 = P64;
+  xf.spec = R.spec.p;
+  launch_xfwd(g, C.fp32, xf, C.stream);
+  launch_yfft(g, C.fp32, R.spec.p, -1, nullptr, C.stream);
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.op = MID_GREEN;
+  m.spec = R.spec.p;
+  for (int c = 0; c < 9; ++c) {
+    m.mask_keep[c] = mask_keep[c];
+    m.dc_target[c] = target ? target[c] : 0.0;
+  }
+  m.inv_n = 1.0 / (double)g.nvox;
+  launch_mid(g, C.fp32, m, C.stream);
+  launch_yfft(g, C.fp32, R.spec.p, +1, nullptr, C.stream);
+  XInvArgs xi;
+  std::memset(&xi, 0, sizeof(xi));
+  xi.mode = XI_RESID;
+  xi.spec = R.spec.p;
+  xi.x = x_zero;
+  xi.r = R.r.p;
+  xi.p = R.p.p;
+  xi.partial = R.partial.as<double>();
+  launch_xinv(g, C.fp32, xi, C.stream);
+  launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), xinv_blocks(g), 0.0, 0, C.stream);
+  check_launch("residual");
+  HIPCHECK(hipMemcpyAsync(C.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
+  HIPCHECK(hipStreamSynchronize(C.stream));
+  return C.host_cg->rr;
+}
+
+// conjugate gradients on G(K : x) = r (x, r, p set by run_residual); returns iterations
+static int run_cg(Ctx& C, RVE& R, void* x, const double* mask_keep, int& done_code) {
+  const GridPlan& g = R.plan.g;
+  CGState* cg = R.cg.as<CGState>();
+  double* part = R.partial.as<double>();
+  const int nb = xfwd_blocks(g);
+  // restart the CG bookkeeping from the residual just computed
+  {
+    CGState s = *C.host_cg;
+    s.iter = 0;
+    s.done = (s.rr0 > 0.0 && C.opt.max_cg > 0) ? 0 : 1;
+    s.tol2 = C.opt.cg_tol * C.opt.cg_tol;
+    s.max_iter = C.opt.max_cg;
+    *C.host_cg = s;
+    HIPCHECK(hipMemcpyAsync(cg, C.host_cg, sizeof(CGState), hipMemcpyHostToDevice, C.stream));
+  }
+  XFwdArgs xf;
+  std::memset(&xf, 0, sizeof(xf));
+  xf.mode = XF_CG;
+  xf.K = R.K.p;
+  xf.gid = R.d_gid.as<int32_t>();
+  xf.grainR = R.d_R.as<double>();
+  xf.r = R.r.p;
+  xf.p = R.p.p;
+  xf.cg = cg;
+  xf.partial = part;
+  xf.spec = R.spec.p;
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.op = MID_GREEN;
+  m.spec = R.spec.p;
+  for (int c = 0; c < 9; ++c) m.mask_keep[c] = mask_keep[c];
+  m.inv_n = 1.0 / (double)g.nvox;
+  m.cg = cg;
+  XInvArgs xi;
+  std::memset(&xi, 0, sizeof(xi));
+  xi.mode = XI_CG;
+  xi.spec = R.spec.p;
+  xi.x = x;
+  xi.r = R.r.p;
+  xi.p = R.p.p;
+  xi.cg = cg;
+  xi.partial = part;
+  const int chunk = 4;
+  for (;;) {
+    if (C.host_cg->done) break;
+    for (int i = 0; i < chunk; ++i) {
+      launch_xfwd(g, C.fp32, xf, C.stream);
+      launch_cg_alpha(cg, part, nb, C.stream);
+      launch_yfft(g, C.fp32, R.spec.p, -1, cg, C.stream);
+      launch_mid(g, C.fp32, m, C.stream);
+      launch_yfft(g, C.fp32, R.spec.p, +1, cg, C.stream);
+      launch_xinv(g, C.fp32, xi, C.stream);
+      launch_cg_beta(cg, part, nb, C.stream);
+    }
+    check_launch("cg");
+    HIPCHECK(hipMemcpyAsync(C.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
+    HIPCHECK(hipStreamSynchronize(C.stream));
+  }
+  done_code = C.host_cg->done;
+  return C.host_cg->iter;
+}
+
+static double rms_of(Ctx& C, RVE& R, const void* f, int64_t n) {
+  const int nb = launch_sumsq(f, C.fp32, n, R.partial.as<double>(), C.stream);
+  std::vector<double> part(nb);
+  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * nb, hipMemcpyDeviceToHost, C.stream));
+  HIPCHECK(hipStreamSynchronize(C.stream));
+  double s = 0.0;
+  for (double v : part) s += v;
+  return std::sqrt(s / (double)n);
+}
+
+static void field_average(Ctx& C, RVE& R, const double* f, int ncomp, double* out) {
+  const int nb = launch_colsum(f, ncomp, R.nvox, R.partial.as<double>(), C.stream);
+  std::vector<double> part((size_t)nb * ncomp);
+  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, C.stream));
+  HIPCHECK(hipStreamSynchronize(C.stream));
+  for (int c = 0; c < ncomp; ++c) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * ncomp + c];
+    out[c] = s / (double)R.nvox;
+  }
+}
+
+static void run_nye(Ctx& C, RVE& R) {
+  const GridPlan& g = R.plan.g;
+  XFwdArgs xf;
+  std::memset(&xf, 0, sizeof(xf));
+  xf.mode = XF_FP_MINUS_I;
+  xf.in64 = R.Fp.as<double>();
+  xf.spec = R.spec.p;
+  launch_xfwd(g, C.fp32, xf, C.stream);
+  launch_yfft(g, C.fp32, R.spec.p, -1, nullptr, C.stream);
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.op = MID_CURL;
+  m.spec = R.spec.p;
+  m.inv_n = 1.0 / (double)g.nvox;
+  m.inv_h = 1.0 / R.h;
+  launch_mid(g, C.fp32, m, C.stream);
+  launch_yfft(g, C.fp32, R.spec.p, +1, nullptr, C.stream);
+  XInvArgs xi;
+  std::memset(&xi, 0, sizeof(xi));
+  xi.mode = XI_NYE;
+  xi.spec = R.spec.p;
+  xi.out64 = R.nye.as<double>();
+  xi.rho_gnd = R.rho_gnd.as<double>();
+  xi.gid = R.d_gid.as<int32_t>();
+  xi.grainR = R.d_R.as<double>();
+  xi.mat = R.d_mat.as<MatDev>();
+  launch_xinv(g, C.fp32, xi, C.stream);
+  check_launch("nye");
+}
+
+// ------------------------------------------------------------------------------------
+// one increment of one RVE (Section 2.2)
+// ------------------------------------------------------------------------------------
+static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask, const double* Pbar, double dt,
+                        rve_step_stats& st) {
+  std::memset(&st, 0, sizeof(st));
+  const int64_t nv = R.nvox;
+  const double n9 = 9.0 * (double)nv;
+  double keep[9], corr[9];
+  for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+  // initial guess: previous field increment, deformation-controlled averages set to the target
+  Corr9 cr;
+  for (int c = 0; c < 9; ++c) {
+    const double dmac = mask[c] ? (Fbar[c] - R.Fbar_prev[c]) : 0.0;
+    const double dprev = R.have_prev ? (R.Favg[c] - R.Favg_prev[c]) : 0.0;
+    corr[c] = mask[c] ? (dmac - dprev) : 0.0;
+    cr.v[c] = corr[c];
+  }
+  HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+  launch_predictor(R.F.as<double>(), R.have_prev ? R.F_prev.as<double>() : nullptr, cr, R.F_work.as<double>(), nv,
+                   C.stream);
+  check_launch("predictor");
+  auto fail = [&](int32_t code, const char* why) {
+    HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+    HIPCHECK(hipStreamSynchronize(C.stream));
+    st.status = code;
+    g_last_error = why;
+    return code;
+  };
+  LocalStats ls = run_constitutive(C, R, R.F_work.as<double>(), nullptr, 0.0, nullptr, dt, true);
+  st.local_iters_max = std::max(st.local_iters_max, ls.max_iters);
+  if (ls.failures) return fail(RVE_ENOCONV, "local Newton did not converge at the initial guess");
+  void* x = R.xa.p;     // CG unknown of the current Newton step
+  void* xo = R.xb.p;    // the other one
+  double rr = run_residual(C, R, R.P_work.as<double>(), keep, Pbar, x);
+  st.residual_evals++;
+  double res = std::sqrt(rr / n9);
+  bool converged = false;
+  for (int it = 0; it < C.opt.max_newton; ++it) {
+    int done = 0;
+    st.cg_iters += run_cg(C, R, x, keep, done);
+    if (done == 3) return fail(RVE_ENOCONV, "conjugate gradients produced a non-finite residual");
+    const double dF = rms_of(C, R, x, 9 * nv);
+    if (!std::isfinite(dF)) return fail(RVE_ENOCONV, "non-finite Newton correction");
+    st.newton_iters++;
+    double lam = 1.0, res_try = 0.0;
+    bool accepted = false;
+    for (int ls_i = 0; ls_i <= C.opt.max_backtrack; ++ls_i) {
+      LocalStats l2 = run_constitutive(C, R, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true);
+      st.local_iters_max = std::max(st.local_iters_max, l2.max_iters);
+      if (l2.failures == 0) {
+        const double rr_t = run_residual(C, R, R.P_work.as<double>(), keep, Pbar, xo);
+        st.residual_evals++;
+        res_try = std::sqrt(rr_t / n9);
+        if (res_try <= res || lam * dF <= C.opt.newton_tol) {
+          accepted = true;
+          break;
+        }
+      }
+      lam *= 0.5;
+      st.line_search_cuts++;
+    }
+    if (!accepted) return fail(RVE_ENOCONV, "residual line search failed");
+    std::swap(R.F_work.p, R.F_try.p);
+    std::swap(x, xo);
+    res = res_try;
+    st.dF_norm = lam * dF;
+    st.res_norm = res;
+    if (lam * dF <= C.opt.newton_tol) {
+      converged = true;
+      break;
+    }
+  }
+  if (!converged) return fail(RVE_ENOCONV, "Newton did not converge within max_newton");
+  // commit: Fp and rho_SSD from the converged slip increments, then the Nye tensor
+  CommitArgs ca;
+  ca.nvox = nv;
+  ca.gid = R.d_gid.as<int32_t>();
+  ca.grainR = R.d_R.as<double>();
+  ca.mat = R.d_mat.as<MatDev>();
+  ca.dg = R.dg.as<double>();
+  ca.Fp = R.Fp.as<double>();
+  ca.rho_ssd = R.rho_ssd.as<double>();
+  ca.rho_gnd = R.rho_gnd.as<double>();
+  launch_commit(ca, C.stream);
+  check_launch("commit");
+  std::swap(R.F_prev.p, R.F.p);     // F_prev <- F_{k-1}
+  std::swap(R.F.p, R.F_work.p);     // F <- F_k
+  std::swap(R.P.p, R.P_work.p);
+  run_nye(C, R);
+  std::memcpy(R.Favg_prev, R.Favg, sizeof(R.Favg));
+  field_average(C, R, R.F.as<double>(), 9, R.Favg);
+  field_average(C, R, R.P.as<double>(), 9, R.Pavg);
+  std::memcpy(R.Fbar_prev, Fbar, sizeof(double) * 9);
+  R.have_prev = true;
+  R.increments++;
+  st.status = RVE_OK;
+  st.voxel_iterations = (double)nv * (double)(st.residual_evals + st.cg_iters);
+  return RVE_OK;
+}
+
+}  // namespace rve
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+using namespace rve;
+
+struct rve_ctx : Ctx {};
+
+template <typename Fn>
+static int32_t guarded(Fn fn) {
+  try {
+    g_last_error.clear();
+    return fn();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return RVE_EDEVICE;
+  }
+}
+
+extern "C" {
+
+int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt, rve_handle* out) {
+  return guarded([&]() -> int32_t {
+    if (!descs || n_rve < 1 || !out) throw Error(RVE_EINVAL, "need descs, n_rve >= 1 and out");
+    std::unique_ptr<rve_ctx> C(new rve_ctx());
+    rve_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.precision = RVE_FP64;
+    o.newton_tol = 1e-10;
+    o.cg_tol = 1e-8;
+    o.max_newton = 40;
+    o.max_cg = 2000;
+    o.max_backtrack = 12;
+    if (opt) o = *opt;
+    if (o.precision != RVE_FP64 && o.precision != RVE_MIXED) throw Error(RVE_EINVAL, "unknown precision");
+    if (!(o.newton_tol > 0) || !(o.cg_tol > 0) || o.max_newton < 1 || o.max_cg < 1 || o.max_backtrack < 0)
+      throw Error(RVE_EINVAL, "bad solver options");
+    C->opt = o;
+    C->fp32 = o.precision == RVE_MIXED;
+    C->device = o.device;
+    HIPCHECK(hipSetDevice(C->device));
+    if (o.stream) {
+      C->stream = (hipStream_t)o.stream;
+    } else {
+      HIPCHECK(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking));
+      C->own_stream = true;
+    }
+    HIPCHECK(hipHostMalloc((void**)&C->host_cg, sizeof(CGState), hipHostMallocDefault));
+    for (int i = 0; i < n_rve; ++i) {
+      C->rves.emplace_back(new RVE());
+      init_rve(*C, *C->rves.back(), descs[i]);
+    }
+    *out = C.release();
+    return RVE_OK;
+  });
+}
+
+void rve_destroy(rve_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  h->rves.clear();
+  if (h->host_cg) (void)hipHostFree(h->host_cg);
+  if (h->own_stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char* rve_last_error(void) { return g_last_error.c_str(); }
+
+int32_t rve_step_increment(rve_handle h, const double* F_bar, const uint8_t* mask, const double* P_bar, double dt,
+                           rve_step_stats* stats) {
+  return guarded([&]() -> int32_t {
+    if (!h || !F_bar || !mask) throw Error(RVE_EINVAL, "null argument");
+    if (!(std::isfinite(dt) && dt > 0)) throw Error(RVE_EINVAL, "dt must be > 0");
+    const int nr = (int)h->rves.size();
+    for (int i = 0; i < 9 * nr; ++i)
+      if (!std::isfinite(F_bar[i]) || (P_bar && !std::isfinite(P_bar[i])))
+        throw Error(RVE_EINVAL, "non-finite load target");
+    HIPCHECK(hipSetDevice(h->device));
+    std::vector<double> zeros(9 * (size_t)nr, 0.0);
+    const double* Pb = P_bar ? P_bar : zeros.data();
+    int32_t worst = RVE_OK;
+    std::string msg;
+    for (int i = 0; i < nr; ++i) {
+      rve_step_stats s;
+      const int32_t rc = step_rve(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, s);
+      if (stats) stats[i] = s;
+      if (rc != RVE_OK) {
+        worst = rc;
+        msg = "rve " + std::to_string(i) + ": " + g_last_error;
+      }
+    }
+    if (worst != RVE_OK) throw Error(worst, msg);
+    return RVE_OK;
+  });
+}
+
+int32_t rve_macro_stress(rve_handle h, int32_t rve, double* P_avg, double* F_avg, double* sigma) {
+  return guarded([&]() -> int32_t {
+    if (!h || rve < 0 || rve >= (int32_t)h->rves.size()) throw Error(RVE_EINVAL, "bad rve index");
+    const RVE& R = *h->rves[rve];
+    if (P_avg) std::memcpy(P_avg, R.Pavg, sizeof(double) * 9);
+    if (F_avg) std::memcpy(F_avg, R.Favg, sizeof(double) * 9);
+    if (sigma) {
+      const double* F = R.Favg;
+      const double det = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                         F[2] * (F[3] * F[7] - F[4] * F[6]);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double s = 0.0;
+          for (int k = 0; k < 3; ++k) s += R.Pavg[3 * i + k] * F[3 * j + k];
+          sigma[3 * i + j] = s / det;
+        }
+    }
+    return RVE_OK;
+  });
+}
+
+int32_t rve_get_field(rve_handle h, int32_t rve, int32_t which, double* out) {
+  return guarded([&]() -> int32_t {
+    if (!h || rve < 0 || rve >= (int32_t)h->rves.size() || !out) throw Error(RVE_EINVAL, "bad argument");
+    RVE& R = *h->rves[rve];
+    const DevBuf* b = nullptr;
+    int nc = 9;
+    switch (which) {
+      case 0: b = &R.F; break;
+      case 1: b = &R.P; break;
+      case 2: b = &R.Fp; break;
+      case 3: b = &R.rho_ssd; nc = 12; break;
+      case 4: b = &R.rho_gnd; nc = 12; break;
+      case 5: b = &R.nye; break;
+      case 6: b = &R.dg; nc = 12; break;
+      default: throw Error(RVE_EINVAL, "unknown field");
+    }
+    HIPCHECK(hipSetDevice(h->device));
+    HIPCHECK(hipMemcpyAsync(out, b->p, sizeof(double) * nc * R.nvox, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_nye_gnd(rve_handle h, int32_t rve, double* nye, double* rho_gnd) {
+  int32_t rc = RVE_OK;
+  if (nye) rc = rve_get_field(h, rve, 5, nye);
+  if (rc == RVE_OK && rho_gnd) rc = rve_get_field(h, rve, 4, rho_gnd);
+  return rc;
+}
+
+// state: per RVE F, F_prev, Fp (9 each), rho_ssd, rho_gnd, dg (12 each), nye, P (9 each),
+// followed by the host scalars.
+int64_t rve_state_bytes(rve_handle h) {
+  if (!h) return 0;
+  int64_t b = 0;
+  for (auto& r : h->rves) b += (int64_t)sizeof(double) * (9 * 5 + 12 * 3) * r->nvox + (int64_t)sizeof(double) * 40;
+  return b;
+}
+
+int32_t rve_save_state(rve_handle h, void* buf) {
+  return guarded([&]() -> int32_t {
+    if (!h || !buf) throw Error(RVE_EINVAL, "null argument");
+    HIPCHECK(hipSetDevice(h->device));
+    char* o = (char*)buf;
+    for (auto& rp : h->rves) {
+      RVE& R = *rp;
+      const DevBuf* bufs[8] = {&R.F, &R.F_prev, &R.Fp, &R.nye, &R.P, &R.rho_ssd, &R.rho_gnd, &R.dg};
+      const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
+      for (int i = 0; i < 8; ++i) {
+        const size_t n = sizeof(double) * nc[i] * R.nvox;
+        HIPCHECK(hipMemcpyAsync(o, bufs[i]->p, n, hipMemcpyDeviceToHost, h->stream));
+        o += n;
+      }
+      double sc[40] = {0};
+      std::memcpy(sc, R.Favg, 72);
+      std::memcpy(sc + 9, R.Favg_prev, 72);
+      std::memcpy(sc + 18, R.Pavg, 72);
+      std::memcpy(sc + 27, R.Fbar_prev, 72);
+      sc[36] = R.have_prev ? 1.0 : 0.0;
+      sc[37] = (double)R.increments;
+      std::memcpy(o, sc, sizeof(sc));
+      o += sizeof(sc);
+    }
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_load_state(rve_handle h, const void* buf) {
+  return guarded([&]() -> int32_t {
+    if (!h || !buf) throw Error(RVE_EINVAL, "null argument");
+    HIPCHECK(hipSetDevice(h->device));
+    const char* o = (const char*)buf;
+    for (auto& rp : h->rves) {
+      RVE& R = *rp;
+      DevBuf* bufs[8] = {&R.F, &R.F_prev, &R.Fp, &R.nye, &R.P, &R.rho_ssd, &R.rho_gnd, &R.dg};
+      const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
+      for (int i = 0; i < 8; ++i) {
+        const size_t n = sizeof(double) * nc[i] * R.nvox;
+        HIPCHECK(hipMemcpyAsync(bufs[i]->p, o, n, hipMemcpyHostToDevice, h->stream));
+        o += n;
+      }
+      double sc[40];
+      std::memcpy(sc, o, sizeof(sc));
+      o += sizeof(sc);
+      std::memcpy(R.Favg, sc, 72);
+      std::memcpy(R.Favg_prev, sc + 9, 72);
+      std::memcpy(R.Pavg, sc + 18, 72);
+      std::memcpy(R.Fbar_prev, sc + 27, 72);
+      R.have_prev = sc[36] != 0.0;
+      R.increments = (int64_t)sc[37];
+    }
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return RVE_OK;
+  });
+}
+
+// ---- kernel-level entry points ------------------------------------------------------
+
+int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const double* grain_quat, int64_t nvox,
+                               const int32_t* gid, const double* F, const double* Fp_n, const double* rho_ssd_n,
+                               const double* rho_gnd_n, double dt, double* dg, double* P, double* K, int32_t* iters,
+                               void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!mat || n_grains < 1 || !grain_quat || nvox < 1 || !gid || !F || !Fp_n || !rho_ssd_n || !rho_gnd_n || !dg ||
+        !P)
+      throw Error(RVE_EINVAL, "null argument");
+    if (!(std::isfinite(dt) && dt > 0)) throw Error(RVE_EINVAL, "dt must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    MatDev md = make_material(*mat);
+    std::vector<double> Rg(9 * (size_t)n_grains);
+    for (int g = 0; g < n_grains; ++g) quat_to_R(grain_quat + 4 * g, &Rg[9 * g]);
+    DevBuf dmat, dR, Kc;
+    upload(dmat, &md, sizeof(md));
+    upload(dR, Rg.data(), sizeof(double) * Rg.size());
+    if (K) Kc.alloc(sizeof(double) * 81 * nvox);
+    ConstArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nvox = nvox;
+    a.gid = gid;
+    a.grainR = dR.as<double>();
+    a.mat = dmat.as<MatDev>();
+    a.F = F;
+    a.Fp_n = Fp_n;
+    a.rho_ssd = rho_ssd_n;
+    a.rho_gnd = rho_gnd_n;
+    a.dg = dg;
+    a.P = P;
+    a.K = K ? Kc.p : nullptr;
+    a.dt = dt;
+    a.iters = iters;
+    launch_constitutive(a, false, st);
+    check_launch("constitutive");
+    if (K) {
+      launch_rotate_tangent(nvox, gid, dR.as<double>(), Kc.as<double>(), K, st);
+      check_launch("rotate tangent");
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
+                    const double* dc_target, double* out, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!n || !A || !mask || !out) throw Error(RVE_EINVAL, "null argument");
+    const bool fp32 = precision == RVE_MIXED;
+    hipStream_t st = (hipStream_t)stream;
+    Plan P;
+    build_plan(P, n, fp32);
+    const GridPlan& g = P.g;
+    DevBuf spec;
+    spec.alloc(tsize(fp32) * 2 * 9 * g.nspec);
+    XFwdArgs xf;
+    std::memset(&xf, 0, sizeof(xf));
+    xf.mode = XF_FIELD64;
+    xf.in64 = A;
+    xf.spec = spec.p;
+    launch_xfwd(g, fp32, xf, st);
+    launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_GREEN;
+    m.spec = spec.p;
+    for (int c = 0; c < 9; ++c) {
+      m.mask_keep[c] = mask[c] ? 0.0 : 1.0;
+      m.dc_target[c] = dc_target ? dc_target[c] : 0.0;
+    }
+    m.inv_n = 1.0 / (double)g.nvox;
+    launch_mid(g, fp32, m, st);
+    launch_yfft(g, fp32, spec.p, +1, nullptr, st);
+    XInvArgs xi;
+    std::memset(&xi, 0, sizeof(xi));
+    xi.mode = XI_OUT64;
+    xi.spec = spec.p;
+    xi.out64 = out;
+    launch_xinv(g, fp32, xi, st);
+    check_launch("project");
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const double* Fp, double* nye,
+                          const int32_t* gid, int32_t n_grains, const double* grain_quat, double burgers,
+                          double* rho_gnd, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!n || !Fp || !nye) throw Error(RVE_EINVAL, "null argument");
+    if (!(std::isfinite(h) && h > 0)) throw Error(RVE_EINVAL, "h must be > 0");
+    const bool fp32 = precision == RVE_MIXED;
+    hipStream_t st = (hipStream_t)stream;
+    Plan P;
+    build_plan(P, n, fp32);
+    const GridPlan& g = P.g;
+    DevBuf spec, dmat, dR;
+    spec.alloc(tsize(fp32) * 2 * 9 * g.nspec);
+    const bool gnd = rho_gnd && gid && grain_quat && n_grains > 0;
+    if (gnd) {
+      if (!(burgers > 0)) throw Error(RVE_EINVAL, "burgers must be > 0");
+      MatDev md;
+      std::memset(&md, 0, sizeof(md));
+      md.burgers = burgers;
+      segment_pinv(md.Aplus, md.screw_of);
+      std::vector<double> Rg(9 * (size_t)n_grains);
+      for (int gi = 0; gi < n_grains; ++gi) quat_to_R(grain_quat + 4 * gi, &Rg[9 * gi]);
+      upload(dmat, &md, sizeof(md));
+      upload(dR, Rg.data(), sizeof(double) * Rg.size());
+    }
+    XFwdArgs xf;
+    std::memset(&xf, 0, sizeof(xf));
+    xf.mode = XF_FP_MINUS_I;
+    xf.in64 = Fp;
+    xf.spec = spec.p;
+    launch_xfwd(g, fp32, xf, st);
+    launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_CURL;
+    m.spec = spec.p;
+    m.inv_n = 1.0 / (double)g.nvox;
+    m.inv_h = 1.0 / h;
+    launch_mid(g, fp32, m, st);
+    launch_yfft(g, fp32, spec.p, +1, nullptr, st);
+    XInvArgs xi;
+    std::memset(&xi, 0, sizeof(xi));
+    xi.mode = XI_NYE;
+    xi.spec = spec.p;
+    xi.out64 = nye;
+    if (gnd) {
+      xi.rho_gnd = rho_gnd;
+      xi.gid = gid;
+      xi.grainR = dR.as<double>();
+      xi.mat = dmat.as<MatDev>();
+    }
+    launch_xinv(g, fp32, xi, st);
+    check_launch("curl");
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Plans and launchers of the spectral path (3-D FFTs, projection, curl, CG updates).
+#pragma once
+
+#include "fft.h"
+#include "kernels.h"
+
+namespace rve {
+
+// Real 9-component fields (nvox each) <-> half spectrum (nz, ny, nxh), nxh = nx/2 + 1.
+struct GridPlan {
+  int nx, ny, nz, nxh;
+  int64_t nvox, nspec;
+  AxisPlan ax, ay, az;
+  const void* twx;   // exp(-2 pi i k / n), n entries, in the spectral precision
+  const void* twy;
+  const void* twz;
+  const void* Ex;    // exp(+2 pi i q / n) for the modified frequencies (A.4), FP64
+  const void* Ey;
+  const void* Ez;
+  int ly;            // rows per block in the x passes (even)
+  int ty;            // kx columns per block in the y passes
+  int tz;            // kx columns per block in the z pass
+};
+
+// Device-resident scalars of the conjugate-gradient loop (FP64).
+struct CGState {
+  double rr;       // r . r of the current residual
+  double rr0;      // r . r of the right-hand side
+  double pKp;      // p . K p  (= p . G(K p) because p lies in the range of G)
+  double alpha, beta;
+  double tol2;     // stop when rr <= tol2 * rr0
+  int32_t iter;
+  int32_t done;
+  int32_t max_iter;
+  int32_t pad;
+};
+
+enum XFwdMode { XF_FIELD64 = 0, XF_CG = 1, XF_FP_MINUS_I = 2 };
+enum XInvMode { XI_RESID = 0, XI_CG = 1, XI_NYE = 2, XI_OUT64 = 3 };
+enum MidOp { MID_GREEN = 0, MID_CURL = 1 };
+
+struct XFwdArgs {
+  int mode;
+  const double* in64;          // XF_FIELD64 / XF_FP_MINUS_I input, 9 x nvox
+  const void* K;               // XF_CG: crystal-frame tangent (T), 81 x nvox
+  const int32_t* gid;          // XF_CG: grain ids for the frame rotation
+  const double* grainR;
+  const void* r;               // XF_CG: residual (T)
+  void* p;                     // XF_CG: search direction (T), updated p = r + beta p
+  CGState* cg;
+  double* partial;             // XF_CG: per-block p.Kp
+  void* spec;                  // out: half spectrum (complex T)
+};
+
+struct MidArgs {
+  int op;
+  void* spec;
+  double mask_keep[9];         // 1 where the average is stress-controlled (kept)
+  double dc_target[9];         // prescribed average of the kept components
+  double inv_n;                // 1 / nvox
+  double inv_h;                // MID_CURL: 1 / voxel size
+  const CGState* cg;           // skip when cg && cg->done
+};
+
+struct XInvArgs {
+  int mode;
+  const void* spec;
+  void* x;                     // XI_RESID / XI_CG (T)
+  void* r;
+  void* p;
+  CGState* cg;
+  double* partial;             // per-block r.r
+  double* out64;               // XI_OUT64 / XI_NYE: 9 x nvox FP64
+  double* rho_gnd;             // XI_NYE: 12 x nvox
+  const int32_t* gid;
+  const double* grainR;
+  const MatDev* mat;
+};
+
+void launch_xfwd(const GridPlan& g, bool fp32, const XFwdArgs& a, hipStream_t st);
+void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGState* cg, hipStream_t st);
+void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st);
+void launch_xinv(const GridPlan& g, bool fp32, const XInvArgs& a, hipStream_t st);
+int xfwd_blocks(const GridPlan& g);
+int xinv_blocks(const GridPlan& g);
+
+// CG bookkeeping kernels (one block).
+void launch_cg_alpha(CGState* cg, const double* partial, int n, hipStream_t st);
+void launch_cg_beta(CGState* cg, const double* partial, int n, hipStream_t st);
+void launch_cg_start(CGState* cg, const double* partial, int n, double tol2, int max_iter, hipStream_t st);
+
+// Sums of a 9- or 12-component FP64 field (per-block partials, reduced on the host),
+// and sum of squares of a T field.
+int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hipStream_t st);
+int launch_sumsq(const void* f, bool fp32, int64_t n, double* partial, hipStream_t st);
+
+// Initial guess of an increment: out = 2 F - F_prev + corr (F + corr when F_prev is null).
+struct Corr9 {
+  double v[9];
+};
+void launch_predictor(const double* F, const double* F_prev, Corr9 corr, double* out, int64_t nvox,
+                      hipStream_t st);
+
+}  // namespace rve

@@ -1,0 +1,105 @@
+"""Kernel-level parity of the HIP library against the oracle (GPU only)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import constitutive as cst
+from oracle import nye as onye
+from oracle import spectral
+from tests.gpu_util import cuda, from_abi, rel_norm, to_abi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01946_amd as m
+    m.lib()
+    return m
+
+
+def _points(V, amp, seed, mat):
+    q = synth.shoemake_quaternions(synth.SplitMix64(seed), 5)
+    model = cst.MaterialModel(mat, q)
+    gid = (np.arange(V) % 5).astype(np.int32)
+    F = synth.random_deformations(seed + 1, V, amp).reshape(V, 3, 3)
+    Fp_n = synth.random_deformations(seed + 2, V, 2e-4).reshape(V, 3, 3)
+    rs = model.rho0 * (1 + synth.random_field(seed + 3, (V, 12), 0, 1))
+    rg = synth.random_field(seed + 4, (V, 12), 0, 1) * 1e12
+    dg0 = synth.random_field(seed + 5, (V, 12), -1e-5, 1e-5)
+    return q, model, gid, F, Fp_n, rs, rg, dg0
+
+
+@pytest.mark.parametrize("amp,hard", [(3e-4, 1), (2e-3, 1), (4e-4, 0)])
+def test_constitutive_update_and_tangent(lib, amp, hard):
+    import torch
+    mat = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=hard)
+    V = 300
+    q, model, gid, F, Fp_n, rs, rg, dg0 = _points(V, amp, 17, mat)
+    dt = 0.5
+    ref = cst.update(model, gid, F, Fp_n, rs, rg, dt, dg0)
+    assert ref["converged"].all()
+    K_ref = cst.tangent_fd(model, gid, F, Fp_n, rs, rg, dt, ref["dg"])
+    t_dg = cuda(to_abi(dg0))
+    t_P = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    t_K = torch.zeros((81, V), dtype=torch.float64, device="cuda:0")
+    t_it = torch.zeros(V, dtype=torch.int32, device="cuda:0")
+    print(f"constitutive V={V} amp={amp} hardening={hard}", flush=True)
+    lib.constitutive_batch(mat, q, cuda(gid), cuda(to_abi(F)), cuda(to_abi(Fp_n)), cuda(to_abi(rs)),
+                           cuda(to_abi(rg)), dt, t_dg, t_P, t_K, t_it)
+    torch.cuda.synchronize()
+    it = t_it.cpu().numpy()
+    assert (it > 0).all(), "some voxels did not converge"
+    dg = from_abi(t_dg.cpu().numpy(), tensor=False)
+    P = from_abi(t_P.cpu().numpy())
+    K = t_K.cpu().numpy().T.reshape(V, 3, 3, 3, 3)
+    scale = np.abs(ref["dg"]).max(axis=1, keepdims=True) + 1e-30
+    assert np.max(np.abs(dg - ref["dg"]) / scale) < 1e-8
+    assert rel_norm(P, ref["P"]) < 1e-11
+    assert np.max(np.abs(P - ref["P"])) < 1e-9 * np.abs(ref["P"]).max()
+    # analytic tangent vs central differences of the oracle
+    err = np.abs(K - K_ref).reshape(V, -1).max(axis=1) / np.abs(K_ref).reshape(V, -1).max(axis=1)
+    assert err.max() < 2e-5
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 4), (10, 12, 6), (16, 16, 16), (64, 64, 64),
+                                   (40, 48, 24)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_projection_matches_oracle(lib, shape, precision):
+    import torch
+    nx, ny, nz = shape
+    A = synth.random_field(3, (nz, ny, nx, 3, 3), -1e7, 1e7)
+    mask = synth.UNIAXIAL_MASK
+    target = np.diag([0.0, 2e6, -1e6])
+    ref = spectral.project(A, mask, target)
+    V = nx * ny * nz
+    out = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    print(f"project shape={shape} precision={precision}", flush=True)
+    lib.project(shape, cuda(to_abi(A.reshape(V, 3, 3))), mask, out, dc_target=target.reshape(9),
+                precision=precision)
+    torch.cuda.synchronize()
+    got = from_abi(out.cpu().numpy()).reshape(nz, ny, nx, 3, 3)
+    tol = 1e-13 if precision == 0 else 2e-6
+    assert rel_norm(got, ref) < tol
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 10, 4), (32, 32, 32)])
+def test_curl_and_gnd_match_oracle(lib, shape):
+    import torch
+    nx, ny, nz = shape
+    V = nx * ny * nz
+    rve = synth.voronoi_rve(7, shape, 5, 1e-6, synth.material("Cu"))
+    Fp = np.eye(3) + 1e-3 * synth.random_field(4, (nz, ny, nx, 3, 3))
+    h = 2.5e-6
+    alpha, seg, rho = onye.gnd_from_fp(Fp, h, rve.grain_of_voxel, rve.quats, 0.256e-9)
+    nye = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    rg = torch.zeros((12, V), dtype=torch.float64, device="cuda:0")
+    print(f"curl shape={shape}", flush=True)
+    lib.spectral_curl(shape, h, cuda(to_abi(Fp.reshape(V, 3, 3))), nye, gid=cuda(rve.grain_of_voxel.reshape(-1)),
+                      quats=rve.quats, burgers=0.256e-9, rho_gnd=rg)
+    torch.cuda.synchronize()
+    assert rel_norm(from_abi(nye.cpu().numpy()), alpha.reshape(V, 3, 3)) < 1e-13
+    assert rel_norm(from_abi(rg.cpu().numpy(), tensor=False), rho.reshape(V, 12)) < 1e-12
