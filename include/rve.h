@@ -99,6 +99,9 @@ typedef struct {
   double res_norm;           /* rms of the final projected residual G(P - P_bar), Pa           */
   double dF_norm;            /* rms of the last applied correction                              */
   double voxel_iterations;   /* nvox * (residual_evals + cg_iters)                              */
+  int32_t fp64_fallback;     /* RVE_MIXED: 1 if the FP32 attempt failed and the increment was
+                                solved with the FP64 spectral path                              */
+  int32_t pad;
 } rve_step_stats;
 
 /* Create a handle holding n_rve RVEs (Section 2.2).  Per grain: rotation from the

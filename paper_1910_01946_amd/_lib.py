@@ -37,7 +37,7 @@ class rve_step_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32),
                 ("residual_evals", C.c_int32), ("line_search_cuts", C.c_int32),
                 ("local_iters_max", C.c_int32), ("res_norm", C.c_double), ("dF_norm", C.c_double),
-                ("voxel_iterations", C.c_double)]
+                ("voxel_iterations", C.c_double), ("fp64_fallback", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

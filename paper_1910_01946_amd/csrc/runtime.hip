@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -299,11 +300,29 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
 
 static size_t tsize(bool fp32) { return fp32 ? 4 : 8; }
 
+// RVE_TRACE=1 in the environment prints one line per Newton iteration to stderr.
+static bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = std::getenv("RVE_TRACE");
+    on = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return on == 1;
+}
+
 // ------------------------------------------------------------------------------------
 // one RVE on the device
 // ------------------------------------------------------------------------------------
-struct RVE {
+// Precision-specific work buffers of one RVE (FP64 or FP32 spectral path).
+struct Work {
+  bool fp32 = false;
+  bool ready = false;
   Plan plan;
+  DevBuf K, xa, xb, r, p, q, spec;
+};
+
+struct RVE {
+  Work w[2];     // [0] FP64, [1] FP32 (allocated on first use)
   int n[3];
   int64_t nvox = 0;
   double h = 0;
@@ -314,7 +333,8 @@ struct RVE {
   // committed state
   DevBuf F, F_prev, Fp, rho_ssd, rho_gnd, nye, dg, P;
   // work
-  DevBuf F_work, F_try, P_work, dg_saved, K, xa, xb, r, p, spec, cg, partial, blk;
+  DevBuf F_work, F_try, P_work, dg_saved, cg, partial, blk;
+  int64_t fp64_fallbacks = 0;
   bool have_prev = false;
   double Favg[9], Favg_prev[9], Pavg[9];
   double Fbar_prev[9];
@@ -336,10 +356,28 @@ static void upload(DevBuf& b, const void* src, size_t bytes) {
   HIPCHECK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
 }
 
+static Work& work(RVE& R, bool fp32) {
+  Work& w = R.w[fp32 ? 1 : 0];
+  if (!w.ready) {
+    w.fp32 = fp32;
+    build_plan(w.plan, R.n, fp32);
+    const int64_t nv = R.nvox;
+    const size_t ts = tsize(fp32);
+    w.K.alloc(ts * 81 * nv);
+    w.xa.alloc(ts * 9 * nv);
+    w.xb.alloc(ts * 9 * nv);
+    w.r.alloc(ts * 9 * nv);
+    w.p.alloc(ts * 9 * nv);
+    w.q.alloc(ts * 9 * nv);
+    w.spec.alloc(ts * 2 * 9 * w.plan.g.nspec);
+    w.ready = true;
+  }
+  return w;
+}
+
 static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   for (int i = 0; i < 3; ++i) R.n[i] = d.n[i];
-  build_plan(R.plan, d.n, C.fp32);
-  R.nvox = R.plan.g.nvox;
+  R.nvox = (int64_t)d.n[0] * d.n[1] * d.n[2];
   if (!(std::isfinite(d.voxel_size) && d.voxel_size > 0)) throw Error(RVE_EINVAL, "voxel_size must be > 0");
   R.h = d.voxel_size;
   if (d.n_grains < 1 || !d.grain_of_voxel || !d.grain_quat) throw Error(RVE_EINVAL, "missing grain data");
@@ -380,17 +418,11 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   R.F_try.alloc(f9);
   R.P_work.alloc(f9);
   R.dg_saved.alloc(f12);
-  const size_t ts = tsize(C.fp32);
-  R.K.alloc(ts * 81 * nv);
-  R.xa.alloc(ts * 9 * nv);
-  R.xb.alloc(ts * 9 * nv);
-  R.r.alloc(ts * 9 * nv);
-  R.p.alloc(ts * 9 * nv);
-  R.spec.alloc(ts * 2 * 9 * R.plan.g.nspec);
+  Work& w = work(R, C.fp32);
   R.cg.alloc(sizeof(CGState));
   HIPCHECK(hipMemset(R.cg.p, 0, sizeof(CGState)));
-  const int nb = std::max(xfwd_blocks(R.plan.g), 1024);
-  R.partial.alloc(sizeof(double) * 12 * nb);
+  const int nb = std::max(xfwd_blocks(w.plan.g), 1024);
+  R.partial.alloc(sizeof(double) * 12 * nb);  // >= 3 x blocks of the x passes, 12 x colsum blocks
   R.blk.alloc(sizeof(int32_t) * 2 * ((nv + 63) / 64));
   for (int i = 0; i < 9; ++i) {
     R.Favg[i] = R.Favg_prev[i] = R.Fbar_prev[i] = (i % 4 == 0) ? 1.0 : 0.0;
@@ -406,7 +438,7 @@ struct LocalStats {
   int failures = 0;
 };
 
-static LocalStats run_constitutive(Ctx& C, RVE& R, const double* F, const void* dF, double lam, double* F_out,
+static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, const void* dF, double lam, double* F_out,
                                    double dt, bool tangent) {
   ConstArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -423,10 +455,10 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, const double* F, const void* 
   a.rho_gnd = R.rho_gnd.as<double>();
   a.dg = R.dg.as<double>();
   a.P = R.P_work.as<double>();
-  a.K = tangent ? R.K.p : nullptr;
+  a.K = tangent ? w.K.p : nullptr;
   a.dt = dt;
   a.blk_stats = R.blk.as<int32_t>();
-  launch_constitutive(a, C.fp32, C.stream);
+  launch_constitutive(a, w.fp32, C.stream);
   check_launch("constitutive");
   const int64_t nb = (R.nvox + 63) / 64;
   std::vector<int32_t> st(2 * nb);
@@ -441,36 +473,36 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, const double* F, const void* 
 }
 
 // projected apply of a stress-like FP64 field: r = -G(P - Pbar), p = r, x = 0; returns r.r
-static double run_residual(Ctx& C, RVE& R, const double* P64, const double* mask_keep, const double* target,
+static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const double* mask_keep, const double* target,
                            void* x_zero) {
-  const GridPlan& g = R.plan.g;
+  const GridPlan& g = w.plan.g;
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
   xf.mode = XF_FIELD64;
   xf.in64 = P64;
-  xf.spec = R.spec.p;
-  launch_xfwd(g, C.fp32, xf, C.stream);
-  launch_yfft(g, C.fp32, R.spec.p, -1, nullptr, C.stream);
+  xf.spec = w.spec.p;
+  launch_xfwd(g, w.fp32, xf, C.stream);
+  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, C.stream);
   MidArgs m;
   std::memset(&m, 0, sizeof(m));
   m.op = MID_GREEN;
-  m.spec = R.spec.p;
+  m.spec = w.spec.p;
   for (int c = 0; c < 9; ++c) {
     m.mask_keep[c] = mask_keep[c];
     m.dc_target[c] = target ? target[c] : 0.0;
   }
   m.inv_n = 1.0 / (double)g.nvox;
-  launch_mid(g, C.fp32, m, C.stream);
-  launch_yfft(g, C.fp32, R.spec.p, +1, nullptr, C.stream);
+  launch_mid(g, w.fp32, m, C.stream);
+  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, C.stream);
   XInvArgs xi;
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_RESID;
-  xi.spec = R.spec.p;
+  xi.spec = w.spec.p;
   xi.x = x_zero;
-  xi.r = R.r.p;
-  xi.p = R.p.p;
+  xi.r = w.r.p;
+  xi.p = w.p.p;
   xi.partial = R.partial.as<double>();
-  launch_xinv(g, C.fp32, xi, C.stream);
+  launch_xinv(g, w.fp32, xi, C.stream);
   launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), xinv_blocks(g), 0.0, 0, C.stream);
   check_launch("residual");
   HIPCHECK(hipMemcpyAsync(C.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
@@ -479,8 +511,8 @@ static double run_residual(Ctx& C, RVE& R, const double* P64, const double* mask
 }
 
 // conjugate gradients on G(K : x) = r (x, r, p set by run_residual); returns iterations
-static int run_cg(Ctx& C, RVE& R, void* x, const double* mask_keep, int& done_code) {
-  const GridPlan& g = R.plan.g;
+static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int& done_code) {
+  const GridPlan& g = w.plan.g;
   CGState* cg = R.cg.as<CGState>();
   double* part = R.partial.as<double>();
   const int nb = xfwd_blocks(g);
@@ -497,41 +529,43 @@ static int run_cg(Ctx& C, RVE& R, void* x, const double* mask_keep, int& done_co
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
   xf.mode = XF_CG;
-  xf.K = R.K.p;
+  xf.K = w.K.p;
   xf.gid = R.d_gid.as<int32_t>();
   xf.grainR = R.d_R.as<double>();
-  xf.r = R.r.p;
-  xf.p = R.p.p;
+  xf.x = x;
+  xf.r = w.r.p;
+  xf.p = w.p.p;
+  xf.q = w.q.p;
   xf.cg = cg;
   xf.partial = part;
-  xf.spec = R.spec.p;
+  xf.spec = w.spec.p;
   MidArgs m;
   std::memset(&m, 0, sizeof(m));
   m.op = MID_GREEN;
-  m.spec = R.spec.p;
+  m.spec = w.spec.p;
   for (int c = 0; c < 9; ++c) m.mask_keep[c] = mask_keep[c];
   m.inv_n = 1.0 / (double)g.nvox;
   m.cg = cg;
   XInvArgs xi;
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_CG;
-  xi.spec = R.spec.p;
-  xi.x = x;
-  xi.r = R.r.p;
-  xi.p = R.p.p;
+  xi.spec = w.spec.p;
+  xi.r = w.r.p;
+  xi.p = w.p.p;
+  xi.q = w.q.p;
   xi.cg = cg;
   xi.partial = part;
   const int chunk = 4;
   for (;;) {
     if (C.host_cg->done) break;
     for (int i = 0; i < chunk; ++i) {
-      launch_xfwd(g, C.fp32, xf, C.stream);
-      launch_cg_alpha(cg, part, nb, C.stream);
-      launch_yfft(g, C.fp32, R.spec.p, -1, cg, C.stream);
-      launch_mid(g, C.fp32, m, C.stream);
-      launch_yfft(g, C.fp32, R.spec.p, +1, cg, C.stream);
-      launch_xinv(g, C.fp32, xi, C.stream);
+      launch_xfwd(g, w.fp32, xf, C.stream);
       launch_cg_beta(cg, part, nb, C.stream);
+      launch_yfft(g, w.fp32, w.spec.p, -1, cg, C.stream);
+      launch_mid(g, w.fp32, m, C.stream);
+      launch_yfft(g, w.fp32, w.spec.p, +1, cg, C.stream);
+      launch_xinv(g, w.fp32, xi, C.stream);
+      launch_cg_alpha(cg, part, nb, C.stream);
     }
     check_launch("cg");
     HIPCHECK(hipMemcpyAsync(C.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
@@ -541,8 +575,8 @@ static int run_cg(Ctx& C, RVE& R, void* x, const double* mask_keep, int& done_co
   return C.host_cg->iter;
 }
 
-static double rms_of(Ctx& C, RVE& R, const void* f, int64_t n) {
-  const int nb = launch_sumsq(f, C.fp32, n, R.partial.as<double>(), C.stream);
+static double rms_of(Ctx& C, RVE& R, Work& w, const void* f, int64_t n) {
+  const int nb = launch_sumsq(f, w.fp32, n, R.partial.as<double>(), C.stream);
   std::vector<double> part(nb);
   HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * nb, hipMemcpyDeviceToHost, C.stream));
   HIPCHECK(hipStreamSynchronize(C.stream));
@@ -563,88 +597,79 @@ static void field_average(Ctx& C, RVE& R, const double* f, int ncomp, double* ou
   }
 }
 
-static void run_nye(Ctx& C, RVE& R) {
-  const GridPlan& g = R.plan.g;
+static void run_nye(Ctx& C, RVE& R, Work& w) {
+  const GridPlan& g = w.plan.g;
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
   xf.mode = XF_FP_MINUS_I;
   xf.in64 = R.Fp.as<double>();
-  xf.spec = R.spec.p;
-  launch_xfwd(g, C.fp32, xf, C.stream);
-  launch_yfft(g, C.fp32, R.spec.p, -1, nullptr, C.stream);
+  xf.spec = w.spec.p;
+  launch_xfwd(g, w.fp32, xf, C.stream);
+  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, C.stream);
   MidArgs m;
   std::memset(&m, 0, sizeof(m));
   m.op = MID_CURL;
-  m.spec = R.spec.p;
+  m.spec = w.spec.p;
   m.inv_n = 1.0 / (double)g.nvox;
   m.inv_h = 1.0 / R.h;
-  launch_mid(g, C.fp32, m, C.stream);
-  launch_yfft(g, C.fp32, R.spec.p, +1, nullptr, C.stream);
+  launch_mid(g, w.fp32, m, C.stream);
+  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, C.stream);
   XInvArgs xi;
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_NYE;
-  xi.spec = R.spec.p;
+  xi.spec = w.spec.p;
   xi.out64 = R.nye.as<double>();
   xi.rho_gnd = R.rho_gnd.as<double>();
   xi.gid = R.d_gid.as<int32_t>();
   xi.grainR = R.d_R.as<double>();
   xi.mat = R.d_mat.as<MatDev>();
-  launch_xinv(g, C.fp32, xi, C.stream);
+  launch_xinv(g, w.fp32, xi, C.stream);
   check_launch("nye");
 }
 
 // ------------------------------------------------------------------------------------
 // one increment of one RVE (Section 2.2)
 // ------------------------------------------------------------------------------------
-static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask, const double* Pbar, double dt,
-                        rve_step_stats& st) {
-  std::memset(&st, 0, sizeof(st));
+// Newton iterations on G(P(F) - P_bar) = 0 from the field in R.F_work, with the average
+// of the deformation-controlled components fixed by that field.  Returns RVE_OK when the
+// applied correction falls below newton_tol; F_work then holds the solution and P_work,
+// dg the matching stress and slip increments.
+static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const double* Pbar, double dt, rve_step_stats& st,
+                            const char** why) {
   const int64_t nv = R.nvox;
   const double n9 = 9.0 * (double)nv;
-  double keep[9], corr[9];
-  for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
-  // initial guess: previous field increment, deformation-controlled averages set to the target
-  Corr9 cr;
-  for (int c = 0; c < 9; ++c) {
-    const double dmac = mask[c] ? (Fbar[c] - R.Fbar_prev[c]) : 0.0;
-    const double dprev = R.have_prev ? (R.Favg[c] - R.Favg_prev[c]) : 0.0;
-    corr[c] = mask[c] ? (dmac - dprev) : 0.0;
-    cr.v[c] = corr[c];
-  }
-  HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
-  launch_predictor(R.F.as<double>(), R.have_prev ? R.F_prev.as<double>() : nullptr, cr, R.F_work.as<double>(), nv,
-                   C.stream);
-  check_launch("predictor");
-  auto fail = [&](int32_t code, const char* why) {
-    HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
-    HIPCHECK(hipStreamSynchronize(C.stream));
-    st.status = code;
-    g_last_error = why;
-    return code;
-  };
-  LocalStats ls = run_constitutive(C, R, R.F_work.as<double>(), nullptr, 0.0, nullptr, dt, true);
+  LocalStats ls = run_constitutive(C, R, w, R.F_work.as<double>(), nullptr, 0.0, nullptr, dt, true);
   st.local_iters_max = std::max(st.local_iters_max, ls.max_iters);
-  if (ls.failures) return fail(RVE_ENOCONV, "local Newton did not converge at the initial guess");
-  void* x = R.xa.p;     // CG unknown of the current Newton step
-  void* xo = R.xb.p;    // the other one
-  double rr = run_residual(C, R, R.P_work.as<double>(), keep, Pbar, x);
+  if (ls.failures) {
+    *why = "local Newton did not converge at the initial guess";
+    return RVE_ENOCONV;
+  }
+  void* x = w.xa.p;     // CG unknown of the current Newton step
+  void* xo = w.xb.p;    // the other one
+  double rr = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, x);
   st.residual_evals++;
   double res = std::sqrt(rr / n9);
-  bool converged = false;
   for (int it = 0; it < C.opt.max_newton; ++it) {
     int done = 0;
-    st.cg_iters += run_cg(C, R, x, keep, done);
-    if (done == 3) return fail(RVE_ENOCONV, "conjugate gradients produced a non-finite residual");
-    const double dF = rms_of(C, R, x, 9 * nv);
-    if (!std::isfinite(dF)) return fail(RVE_ENOCONV, "non-finite Newton correction");
+    const int ncg = run_cg(C, R, w, x, keep, done);
+    const CGState cg_end = *C.host_cg;
+    st.cg_iters += ncg;
+    // A breakdown (negative curvature along p), a diverging residual or the iteration cap
+    // ends CG with its current iterate, as truncated CG does; the residual line search
+    // below decides whether that correction is usable.
+    const double dF = rms_of(C, R, w, x, 9 * nv);
+    if (!std::isfinite(dF)) {
+      *why = "non-finite Newton correction";
+      return RVE_ENOCONV;
+    }
     st.newton_iters++;
     double lam = 1.0, res_try = 0.0;
     bool accepted = false;
     for (int ls_i = 0; ls_i <= C.opt.max_backtrack; ++ls_i) {
-      LocalStats l2 = run_constitutive(C, R, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true);
+      LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true);
       st.local_iters_max = std::max(st.local_iters_max, l2.max_iters);
       if (l2.failures == 0) {
-        const double rr_t = run_residual(C, R, R.P_work.as<double>(), keep, Pbar, xo);
+        const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
         st.residual_evals++;
         res_try = std::sqrt(rr_t / n9);
         if (res_try <= res || lam * dF <= C.opt.newton_tol) {
@@ -655,18 +680,97 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
       lam *= 0.5;
       st.line_search_cuts++;
     }
-    if (!accepted) return fail(RVE_ENOCONV, "residual line search failed");
+    if (trace_on())
+      std::fprintf(stderr,
+                   "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e) |dF| %.3e lam %.4g res %.4e -> %.4e%s local_it %d\n",
+                   it + 1, ncg, done, cg_end.rr / cg_end.rr0, dF, lam, res, res_try,
+                   accepted ? "" : " (line search failed)", st.local_iters_max);
+    if (!accepted) {
+      *why = "residual line search failed";
+      return RVE_ENOCONV;
+    }
     std::swap(R.F_work.p, R.F_try.p);
     std::swap(x, xo);
     res = res_try;
     st.dF_norm = lam * dF;
     st.res_norm = res;
-    if (lam * dF <= C.opt.newton_tol) {
-      converged = true;
-      break;
-    }
+    if (lam * dF <= C.opt.newton_tol) return RVE_OK;
   }
-  if (!converged) return fail(RVE_ENOCONV, "Newton did not converge within max_newton");
+  *why = "Newton did not converge within max_newton";
+  return RVE_ENOCONV;
+}
+
+// Increment k.  The initial guess extrapolates the previous field increment, with the
+// average of the deformation-controlled components set to the target.  If Newton fails
+// from there, the same increment (same dt, same start-of-increment state) is solved again
+// by continuation in the load: targets F_bar(s) = F_bar_{k-1} + s (F_bar_k - F_bar_{k-1})
+// for s = 1/m, 2/m, ..., 1 (m = 2, 4, 8, 16), each solve started from the previous root.
+// Only the s = 1 problem is the increment, so the committed solution is the same.
+static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask, const double* Pbar, double dt,
+                        rve_step_stats& st) {
+  std::memset(&st, 0, sizeof(st));
+  const int64_t nv = R.nvox;
+  double keep[9];
+  for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+  HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+  auto restore_dg = [&]() {
+    HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+  };
+  const char* why = "";
+  auto attempt = [&](Work& w, int max_stages) -> int32_t {
+    // direct attempt
+    Corr9 cr;
+    for (int c = 0; c < 9; ++c) {
+      const double dmac = mask[c] ? (Fbar[c] - R.Fbar_prev[c]) : 0.0;
+      const double dprev = R.have_prev ? (R.Favg[c] - R.Favg_prev[c]) : 0.0;
+      cr.v[c] = mask[c] ? (dmac - dprev) : 0.0;
+    }
+    launch_predictor(R.F.as<double>(), R.have_prev ? R.F_prev.as<double>() : nullptr, cr, R.F_work.as<double>(),
+                     nv, C.stream);
+    check_launch("predictor");
+    int32_t rc = newton_solve(C, R, w, keep, Pbar, dt, st, &why);
+    for (int m = 2; rc != RVE_OK && m <= max_stages; m *= 2) {
+      if (trace_on()) std::fprintf(stderr, "[rve] %s; load continuation with %d stages\n", why, m);
+      restore_dg();
+      Corr9 zero;
+      for (int c = 0; c < 9; ++c) zero.v[c] = 0.0;
+      launch_predictor(R.F.as<double>(), nullptr, zero, R.F_work.as<double>(), nv, C.stream);
+      double Fb_prev[9];
+      std::memcpy(Fb_prev, R.Fbar_prev, sizeof(Fb_prev));
+      rc = RVE_OK;
+      for (int sidx = 1; sidx <= m && rc == RVE_OK; ++sidx) {
+        const double s = (double)sidx / (double)m;
+        Corr9 step;
+        for (int c = 0; c < 9; ++c) {
+          const double target = R.Fbar_prev[c] + s * (Fbar[c] - R.Fbar_prev[c]);
+          step.v[c] = mask[c] ? (target - Fb_prev[c]) : 0.0;
+          Fb_prev[c] = target;
+        }
+        launch_predictor(R.F_work.as<double>(), nullptr, step, R.F_work.as<double>(), nv, C.stream);
+        check_launch("predictor");
+        rc = newton_solve(C, R, w, keep, Pbar, dt, st, &why);
+      }
+    }
+    return rc;
+  };
+  // FP32: one direct attempt, then the FP64 path with load continuation
+  int32_t rc = attempt(work(R, C.fp32), C.fp32 ? 1 : 16);
+  if (rc != RVE_OK && C.fp32) {
+    // FP32 conjugate gradients stall near kappa * eps_32 on ill-conditioned tangents;
+    // solve this increment with the FP64 spectral path instead.
+    if (trace_on()) std::fprintf(stderr, "[rve] %s in FP32; increment solved again in FP64\n", why);
+    restore_dg();
+    st.fp64_fallback = 1;
+    R.fp64_fallbacks++;
+    rc = attempt(work(R, false), 16);
+  }
+  if (rc != RVE_OK) {
+    restore_dg();
+    HIPCHECK(hipStreamSynchronize(C.stream));
+    st.status = rc;
+    g_last_error = why;
+    return rc;
+  }
   // commit: Fp and rho_SSD from the converged slip increments, then the Nye tensor
   CommitArgs ca;
   ca.nvox = nv;
@@ -682,7 +786,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   std::swap(R.F_prev.p, R.F.p);     // F_prev <- F_{k-1}
   std::swap(R.F.p, R.F_work.p);     // F <- F_k
   std::swap(R.P.p, R.P_work.p);
-  run_nye(C, R);
+  run_nye(C, R, work(R, C.fp32));
   std::memcpy(R.Favg_prev, R.Favg, sizeof(R.Favg));
   field_average(C, R, R.F.as<double>(), 9, R.Favg);
   field_average(C, R, R.P.as<double>(), 9, R.Pavg);

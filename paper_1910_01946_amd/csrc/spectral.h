@@ -23,14 +23,25 @@ struct GridPlan {
 };
 
 // Device-resident scalars of the conjugate-gradient loop (FP64).
+//
+// The operator is applied to the residual and the search-direction image follows by
+// linearity, so that every dot product is taken from stored vectors:
+//   forward x pass (iteration k > 0):  x += alpha p,  r -= alpha q;  partial r.r;  K : r
+//   beta kernel:   beta = r.r / (previous r.r);  stop if r.r <= tol2 r0.r0
+//   inverse x pass: w = G(K : r);  q = w + beta q,  p = r + beta p;  partial p.q
+//   alpha kernel:  alpha = r.r / p.q
+// (q = G(K : p) by linearity of the projected operator).  Taking p.q from the projected
+// q keeps alpha consistent with the operator actually applied (p.Kp equals p.G(Kp) only
+// while p lies exactly in the range of G, which FP32 rounding does not preserve), and
+// r.r is summed from the stored residual each iteration.
 struct CGState {
   double rr;       // r . r of the current residual
   double rr0;      // r . r of the right-hand side
-  double pKp;      // p . K p  (= p . G(K p) because p lies in the range of G)
+  double pq;
   double alpha, beta;
   double tol2;     // stop when rr <= tol2 * rr0
-  int32_t iter;
-  int32_t done;
+  int32_t iter;    // completed operator applications
+  int32_t done;    // 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 diverging (r.r > 1e4 r0.r0), 4 max_iter
   int32_t max_iter;
   int32_t pad;
 };
@@ -45,10 +56,12 @@ struct XFwdArgs {
   const void* K;               // XF_CG: crystal-frame tangent (T), 81 x nvox
   const int32_t* gid;          // XF_CG: grain ids for the frame rotation
   const double* grainR;
-  const void* r;               // XF_CG: residual (T)
-  void* p;                     // XF_CG: search direction (T), updated p = r + beta p
+  void* x;                     // XF_CG: solution (T), x += alpha p
+  void* r;                     // XF_CG: residual (T), r -= alpha q
+  const void* p;               // XF_CG: search direction (T)
+  const void* q;               // XF_CG: G(K : p) (T)
   CGState* cg;
-  double* partial;             // XF_CG: per-block p.Kp
+  double* partial;             // XF_CG: per-block r.r
   void* spec;                  // out: half spectrum (complex T)
 };
 
@@ -65,11 +78,12 @@ struct MidArgs {
 struct XInvArgs {
   int mode;
   const void* spec;
-  void* x;                     // XI_RESID / XI_CG (T)
-  void* r;
-  void* p;
+  void* x;                     // XI_RESID (T)
+  void* r;                     // XI_RESID: out; XI_CG: in
+  void* p;                     // XI_RESID: out; XI_CG: p = r + beta p
+  void* q;                     // XI_CG: q = G(K : r) + beta q
   CGState* cg;
-  double* partial;             // per-block r.r
+  double* partial;             // XI_RESID: per-block r.r; XI_CG: per-block p.q
   double* out64;               // XI_OUT64 / XI_NYE: 9 x nvox FP64
   double* rho_gnd;             // XI_NYE: 12 x nvox
   const int32_t* gid;
@@ -85,8 +99,8 @@ int xfwd_blocks(const GridPlan& g);
 int xinv_blocks(const GridPlan& g);
 
 // CG bookkeeping kernels (one block).
-void launch_cg_alpha(CGState* cg, const double* partial, int n, hipStream_t st);
 void launch_cg_beta(CGState* cg, const double* partial, int n, hipStream_t st);
+void launch_cg_alpha(CGState* cg, const double* partial, int n, hipStream_t st);
 void launch_cg_start(CGState* cg, const double* partial, int n, double tol2, int max_iter, hipStream_t st);
 
 // Sums of a 9- or 12-component FP64 field (per-block partials, reduced on the host),

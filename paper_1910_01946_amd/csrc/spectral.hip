@@ -65,22 +65,28 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) val[c] = (T)(a.in64[c * nv + v] - ((c % 4 == 0) ? 1.0 : 0.0));
       } else {
-        const T* r = reinterpret_cast<const T*>(a.r);
-        T* p = reinterpret_cast<T*>(a.p);
+        T* X = reinterpret_cast<T*>(a.x);
+        T* r = reinterpret_cast<T*>(a.r);
+        const T* p = reinterpret_cast<const T*>(a.p);
+        const T* q = reinterpret_cast<const T*>(a.q);
         const T* K = reinterpret_cast<const T*>(a.K);
         double ps[9];
         if (a.cg->iter > 0) {
-          const double beta = a.cg->beta;
+          const double alpha = a.cg->alpha;
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            const T pn = (T)((double)r[c * nv + v] + beta * (double)p[c * nv + v]);
-            p[c * nv + v] = pn;
-            ps[c] = (double)pn;
+            const int64_t o = c * nv + v;
+            X[o] = (T)((double)X[o] + alpha * (double)p[o]);
+            const T rn = (T)((double)r[o] - alpha * (double)q[o]);
+            r[o] = rn;
+            ps[c] = (double)rn;
           }
         } else {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) ps[c] = (double)p[c * nv + v];
+          for (int c = 0; c < 9; ++c) ps[c] = (double)r[c * nv + v];
         }
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc += ps[c] * ps[c];
         const int gi = a.gid[v];
         double Rg[9], pc[9], yc[9], ys[9];
 #pragma unroll
@@ -95,10 +101,7 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
         }
         to_sample(Rg, yc, ys);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          acc += ps[c] * ys[c];
-          val[c] = (T)ys[c];
-        }
+        for (int c = 0; c < 9; ++c) val[c] = (T)ys[c];
       }
     }
 #pragma unroll
@@ -128,8 +131,8 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
     if (ya + 1 < ny) spec[(row0 + ya + 1) * nxh + k] = B;
   }
   if (MODE == XF_CG) {
-    const double s = block_sum<T>(acc, red);
-    if (tid == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    const double sum = block_sum<T>(acc, red);
+    if (tid == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -313,17 +316,30 @@ __global__ void k_xinv(GridPlan g, XInvArgs a) {
           acc += (double)rv * (double)rv;
         }
       } else if (MODE == XI_CG) {
-        T* X = reinterpret_cast<T*>(a.x);
-        T* R = reinterpret_cast<T*>(a.r);
-        const T* P = reinterpret_cast<const T*>(a.p);
-        const double alpha = a.cg->alpha;
+        T* Q = reinterpret_cast<T*>(a.q);
+        const T* R = reinterpret_cast<const T*>(a.r);
+        T* P = reinterpret_cast<T*>(a.p);
+        if (a.cg->iter > 0) {
+          const double beta = a.cg->beta;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const int64_t o = c * nv + v;
-          X[o] = (T)((double)X[o] + alpha * (double)P[o]);
-          const T rv = (T)((double)R[o] - alpha * q[c]);
-          R[o] = rv;
-          acc += (double)rv * (double)rv;
+          for (int c = 0; c < 9; ++c) {
+            const int64_t o = c * nv + v;
+            const T qv = (T)(q[c] + beta * (double)Q[o]);
+            const T pv = (T)((double)R[o] + beta * (double)P[o]);
+            Q[o] = qv;
+            P[o] = pv;
+            acc += (double)pv * (double)qv;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const int64_t o = c * nv + v;
+            const T qv = (T)q[c];
+            const T pv = R[o];
+            Q[o] = qv;
+            P[o] = pv;
+            acc += (double)pv * (double)qv;
+          }
         }
       } else if (MODE == XI_OUT64) {
 #pragma unroll
@@ -390,30 +406,34 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
   }
 }
 
-__global__ void k_cg_alpha(CGState* cg, const double* partial, int n) {
-  if (cg->done) return;
-  const double pKp = reduce_partials(partial, n);
-  if (threadIdx.x == 0) {
-    cg->pKp = pKp;
-    if (pKp > 0.0 && pKp < 1e300) {
-      cg->alpha = cg->rr / pKp;
-    } else {
-      cg->alpha = 0.0;
-      cg->done = 2;  // breakdown: the operator is not positive along p
-    }
-  }
-}
-
 __global__ void k_cg_beta(CGState* cg, const double* partial, int n) {
   if (cg->done) return;
   const double rr = reduce_partials(partial, n);
   if (threadIdx.x == 0) {
-    cg->beta = rr / cg->rr;
+    if (cg->iter == 0) {
+      cg->beta = 0.0;
+    } else {
+      cg->beta = rr / cg->rr;
+    }
     cg->rr = rr;
-    cg->iter += 1;
     if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
-    else if (!(rr < 1e300)) cg->done = 3;
+    else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;  // diverging (or not finite)
     else if (cg->iter >= cg->max_iter) cg->done = 4;
+  }
+}
+
+__global__ void k_cg_alpha(CGState* cg, const double* partial, int n) {
+  if (cg->done) return;
+  const double pq = reduce_partials(partial, n);
+  if (threadIdx.x == 0) {
+    cg->pq = pq;
+    cg->iter += 1;
+    if (pq > 0.0 && pq < 1e300) {
+      cg->alpha = cg->rr / pq;
+    } else {
+      cg->alpha = 0.0;
+      cg->done = 2;  // breakdown: the operator is not positive along p
+    }
   }
 }
 
@@ -553,11 +573,11 @@ void launch_xinv(const GridPlan& g, bool fp32, const XInvArgs& a, hipStream_t st
 void launch_cg_start(CGState* cg, const double* partial, int n, double tol2, int max_iter, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, cg, partial, n, tol2, max_iter);
 }
-void launch_cg_alpha(CGState* cg, const double* partial, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cg, partial, n);
-}
 void launch_cg_beta(CGState* cg, const double* partial, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, cg, partial, n);
+}
+void launch_cg_alpha(CGState* cg, const double* partial, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cg, partial, n);
 }
 
 int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hipStream_t st) {
