@@ -20,7 +20,7 @@
 //   u_b = Ce s_b, w_b = A^{-T} m_b, Chat_a = C : sym(s_a (x) m_a),
 // solved by Gaussian elimination without pivoting (J = D (D^{-1} + M) with M close to a
 // symmetric positive semi-definite Gram matrix, so elimination is stable), steps capped
-// at 0.02 in the max norm and backtracked on |R|.  If 8 Newton steps at the final
+// at 0.02 in the max norm and backtracked on |R|.  If 25 Newton steps at the final
 // exponent do not converge from the warm start, the lane restarts with continuation in
 // the exponent (roots at n = 1, 2, 4, 8, 16, then n = 1/m): far from the solution the
 // Jacobian rows of overloaded systems carry (|tau|/tau_c)^(n-1) and J becomes
@@ -32,6 +32,8 @@
 //   dP = e_k (x) (G S G^T)_l. - Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T.
 #include "common.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace rve {
 
@@ -172,7 +174,8 @@ __device__ __forceinline__ void lu12_solve(const double J[12][12], double* x) {
   }
 }
 
-// Newton iterations at exponent n; returns 1 if converged.  iters accumulates.
+// Newton iterations at exponent n; returns 1 if converged.  iters accumulates.  The line
+// search works in place: a rejected trial dg + lam d is pulled back by lam/2 d.
 __device__ int newton(const Point& p, double n, double tol, int maxit, double* dg, int& iters) {
   const double floor_ = 1e-10, max_step = 0.02;
   Kin k;
@@ -203,185 +206,222 @@ __device__ int newton(const Point& p, double n, double tol, int maxit, double* d
       for (int a = 0; a < 12; ++a) dg[a] += d[a];
       return 1;
     }
-    double lam = 1.0, trial[12];
-    for (int ls = 0; ls < 30; ++ls) {
+    double lam = 1.0;
 #pragma unroll
-      for (int a = 0; a < 12; ++a) trial[a] = dg[a] + lam * d[a];
-      const double rt = residual(p, n, trial, k, R, nullptr);
+    for (int a = 0; a < 12; ++a) dg[a] += d[a];
+    for (int ls = 0; ls < 30; ++ls) {
+      const double rt = residual(p, n, dg, k, R, nullptr);
       if (rt <= r2) break;
       lam *= 0.5;
-    }
 #pragma unroll
-    for (int a = 0; a < 12; ++a) dg[a] = trial[a];
+      for (int a = 0; a < 12; ++a) dg[a] -= lam * d[a];
+    }
   }
   return 0;
 }
 
 }  // namespace
 
-template <typename KT>
-__global__ void __launch_bounds__(64) k_constitutive(ConstArgs args) {
+// Shared set-up of a voxel: frame rotation, Fe0 = F_c Fp_n,c^{-1}, critical stresses.
+__device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev& M, int64_t v, int64_t nv,
+                                            const void* dF, bool dF_fp32, double* Rg, Point& p) {
+  const int g = args.gid[v];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rg[i] = args.grainR[9 * g + i];
+  double Fs[9], Fps[9], Fc[9], Fpc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double f = args.F[i * nv + v];
+    if (dF) f += args.lam * (dF_fp32 ? (double)reinterpret_cast<const float*>(dF)[i * nv + v]
+                                      : reinterpret_cast<const double*>(dF)[i * nv + v]);
+    Fs[i] = f;
+    Fps[i] = args.Fp_n[i * nv + v];
+  }
+  if (args.F_out) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) args.F_out[i * nv + v] = Fs[i];
+  }
+  to_crystal(Rg, Fs, Fc);
+  to_crystal(Rg, Fps, Fpc);
+  p.C11 = M.C11;
+  p.C12 = M.C12;
+  p.C44 = M.C44;
+  p.a = args.dt * M.gamma0_dot;
+  inv3(Fpc, p.Gn);
+  mm3(Fc, p.Gn, p.Fe0);
+  if (M.hardening) {
+    double forest[12];
+#pragma unroll
+    for (int b = 0; b < 12; ++b) forest[b] = args.rho_ssd[b * nv + v] + M.c_gnd * args.rho_gnd[b * nv + v];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < 12; ++b) s += M.q[12 * a + b] * forest[b];
+      p.tc[a] = M.mu * M.burgers * sqrt(s);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) p.tc[a] = M.tau_c_frozen;
+  }
+}
+
+// Local solve, pass 1: Newton at n = 1/m from the warm start, at most kFastIters steps.
+// Converged voxels write their slip increments; the others are appended to a work list
+// (their warm start stays in memory) for the continuation pass, so that a few stiff
+// voxels do not hold whole wavefronts.  stats[0] = largest iteration count (atomic max),
+// stats[1] = failures, stats[2] = length of the work list.
+constexpr int kFastIters = 12;
+
+template <bool DF32>
+__global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
-  __shared__ int s_it[64];
-  __shared__ int s_fail[64];
-  int my_it = 0, my_fail = 0;
-  if (v < nv) {
-    const MatDev& M = *args.mat;
-    const int g = args.gid[v];
-    double Rg[9];
+  if (v >= nv) return;
+  const MatDev& M = *args.mat;
+  double Rg[9];
+  Point p;
+  setup_point(args, M, v, nv, args.dF, DF32, Rg, p);
+  double dg[12];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Rg[i] = args.grainR[9 * g + i];
-    double Fs[9], Fps[9], Fc[9], Fpc[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      double f = args.F[i * nv + v];
-      if (args.dF) f += args.lam * (double)reinterpret_cast<const KT*>(args.dF)[i * nv + v];
-      Fs[i] = f;
-      Fps[i] = args.Fp_n[i * nv + v];
-    }
-    if (args.F_out) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) args.F_out[i * nv + v] = Fs[i];
-    }
-    to_crystal(Rg, Fs, Fc);
-    to_crystal(Rg, Fps, Fpc);
-    Point p;
-    p.C11 = M.C11;
-    p.C12 = M.C12;
-    p.C44 = M.C44;
-    p.a = args.dt * M.gamma0_dot;
-    inv3(Fpc, p.Gn);
-    mm3(Fc, p.Gn, p.Fe0);
-    if (M.hardening) {
-      double forest[12];
-#pragma unroll
-      for (int b = 0; b < 12; ++b) forest[b] = args.rho_ssd[b * nv + v] + M.c_gnd * args.rho_gnd[b * nv + v];
-#pragma unroll
-      for (int a = 0; a < 12; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < 12; ++b) s += M.q[12 * a + b] * forest[b];
-        p.tc[a] = M.mu * M.burgers * sqrt(s);
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < 12; ++a) p.tc[a] = M.tau_c_frozen;
-    }
-    double dg0[12], dg[12];
-#pragma unroll
-    for (int a = 0; a < 12; ++a) dg0[a] = dg[a] = args.dg[a * nv + v];
-    const double n_final = M.n_exp;
-    int it = 0;
-    int ok = newton(p, n_final, 1e-10, 8, dg, it);
-    if (!ok) {
-#pragma unroll
-      for (int a = 0; a < 12; ++a) dg[a] = dg0[a];
-      const double stages[5] = {1.0, 2.0, 4.0, 8.0, 16.0};
-      for (int s = 0; s < 5; ++s) {
-        if (stages[s] >= n_final) break;
-        newton(p, stages[s], 1e-4, 60, dg, it);
-      }
-      ok = newton(p, n_final, 1e-10, 60, dg, it);
-    }
-    my_it = it;
-    my_fail = ok ? 0 : 1;
+  for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+  int it = 0;
+  const int ok = newton(p, M.n_exp, 1e-10, kFastIters, dg, it);
+  if (ok) {
 #pragma unroll
     for (int a = 0; a < 12; ++a) args.dg[a * nv + v] = dg[a];
-    // stress at the converged slip increments
-    Kin k;
-    double R[12], D[12];
-    residual(p, n_final, dg, k, R, D);
-    double G[9], Gt_tmp[9], SGt[9], Pc[9], Ps[9];
-    mm3(p.Gn, k.Ainv, G);            // Fp^{-1}
-    mmt3(k.S, G, SGt);               // S G^T
-    mm3(k.Fe, SGt, Pc);              // P_c = Fe S G^T
-    to_sample(Rg, Pc, Ps);
+    if (args.iters) args.iters[v] = it;
+    atomicMax(&args.stats[0], it);
+  } else {
+    const int slot = atomicAdd(&args.stats[2], 1);
+    args.work[slot] = (int32_t)v;
+  }
+}
+
+// Local solve, pass 2 (work-list voxels): continuation in the exponent from the warm
+// start, roots at n = 1, 2, 4, 8, 16, then Newton at n = 1/m.
+template <bool DF32>
+__global__ void __launch_bounds__(64) k_slip_slow(ConstArgs args) {
+  const int count = args.stats[2];
+  const int64_t nv = args.nvox;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
+    const int64_t v = args.work[idx];
+    const MatDev& M = *args.mat;
+    double Rg[9];
+    Point p;
+    setup_point(args, M, v, nv, args.dF, DF32, Rg, p);
+    double dg[12];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) args.P[i * nv + v] = ok ? Ps[i] : NAN;
-    (void)Gt_tmp;
-    if (args.K && ok) {
-      double J[12][12];
-      jacobian(p, k, D, J);
-      lu12(J);
-      double H[9], Q[9], W[9], AtS[9];
-      mm3(G, SGt, H);                // G S G^T
-      mm3(k.Ainv, SGt, Q);           // A^{-1} S G^T
-      mmt3(k.S, k.Ainv, AtS);        // S A^{-T}
-      mm3(k.Fe, AtS, W);             // Fe S A^{-T}
-      KT* Kout = reinterpret_cast<KT*>(args.K);
+    for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+    const double n_final = M.n_exp;
+    const double stages[5] = {1.0, 2.0, 4.0, 8.0, 16.0};
+    int it = kFastIters, ok = 0;
+    for (int pass = 0; pass < 6; ++pass) {
+      double n = n_final, tol = 1e-10;
+      if (pass < 5) {
+        n = stages[pass];
+        tol = 1e-4;
+        if (n >= n_final) continue;
+      }
+      const int r = newton(p, n, tol, 60, dg, it);
+      if (pass == 5) ok = r;
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) args.dg[a * nv + v] = dg[a];
+    if (args.iters) args.iters[v] = ok ? it : -it - 1;
+    atomicMax(&args.stats[0], it);
+    if (!ok) atomicAdd(&args.stats[1], 1);
+  }
+}
+
+__global__ void k_reset_stats(int32_t* stats) {
+  if (threadIdx.x < 4) stats[threadIdx.x] = 0;
+}
+
+// Stress and consistent tangent at the converged slip increments.
+template <typename KT, bool DF32>
+__global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = args.nvox;
+  if (v >= nv) return;
+  const MatDev& M = *args.mat;
+  double Rg[9];
+  Point p;
+  ConstArgs a2 = args;
+  a2.F_out = nullptr;
+  setup_point(a2, M, v, nv, args.dF, DF32, Rg, p);
+  double dg[12];
+#pragma unroll
+  for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+  Kin k;
+  double R[12], D[12];
+  residual(p, M.n_exp, dg, k, R, D);
+  double G[9], SGt[9], Pc[9], Ps[9];
+  mm3(p.Gn, k.Ainv, G);            // Fp^{-1}
+  mmt3(k.S, G, SGt);               // S G^T
+  mm3(k.Fe, SGt, Pc);              // P_c = Fe S G^T
+  to_sample(Rg, Pc, Ps);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) args.P[i * nv + v] = Ps[i];
+  if (!args.K) return;
+  double J[12][12];
+  jacobian(p, k, D, J);
+  lu12(J);
+  double H[9], Q[9], W[9], AtS[9];
+  mm3(G, SGt, H);                  // G S G^T
+  mm3(k.Ainv, SGt, Q);             // A^{-1} S G^T
+  mmt3(k.S, k.Ainv, AtS);          // S A^{-T}
+  mm3(k.Fe, AtS, W);               // Fe S A^{-T}
+  KT* Kout = reinterpret_cast<KT*>(args.K);
 #pragma unroll 1
-      for (int kk = 0; kk < 3; ++kk) {
+  for (int kk = 0; kk < 3; ++kk) {
 #pragma unroll 1
-        for (int ll = 0; ll < 3; ++ll) {
-          const double av[3] = {k.Fe[3 * kk], k.Fe[3 * kk + 1], k.Fe[3 * kk + 2]};
-          const double bv[3] = {G[3 * ll], G[3 * ll + 1], G[3 * ll + 2]};
-          double x[12];
+    for (int ll = 0; ll < 3; ++ll) {
+      const double av[3] = {k.Fe[3 * kk], k.Fe[3 * kk + 1], k.Fe[3 * kk + 2]};
+      const double bv[3] = {G[3 * ll], G[3 * ll + 1], G[3 * ll + 2]};
+      double x[12];
 #pragma unroll
-          for (int a = 0; a < 12; ++a) x[a] = D[a] * uCw(p, a, av, bv);
-          lu12_solve(J, x);
-          double Z[9];
+      for (int a = 0; a < 12; ++a) x[a] = D[a] * uCw(p, a, av, bv);
+      lu12_solve(J, x);
+      double Z[9];
 #pragma unroll
-          for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              double z = 0.0;
+        for (int j = 0; j < 3; ++j) {
+          double z = 0.0;
 #pragma unroll
-              for (int b = 0; b < 12; ++b) z += x[b] * kSlipS[b][i] * kSlipM[b][j];
-              Z[3 * i + j] = z;
-            }
-          double CeZ[9], CeZA[9], dE[9], dS[9];
-          mm3(k.Ce, Z, CeZ);
-          mm3(CeZ, k.Ainv, CeZA);
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-              dE[3 * i + j] = 0.5 * (av[i] * bv[j] + av[j] * bv[i]) - 0.5 * (CeZA[3 * i + j] + CeZA[3 * j + i]);
-          cubic_stress(p, dE, dS);
-          double t1[9], t2[9], dP[9];
-          // - Fe Z Q
-          mm3(Z, Q, t1);
-          mm3(k.Fe, t1, dP);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) dP[i] = -dP[i];
-          // + Fe dS G^T
-          mmt3(dS, G, t1);
-          mm3(k.Fe, t1, t2);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) dP[i] += t2[i];
-          // - W Z^T G^T = - W (G Z)^T
-          mm3(G, Z, t1);
-          mmt3(W, t1, t2);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
-          // + e_k (x) H_l.
-#pragma unroll
-          for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];
-          const int col = 3 * kk + ll;
-#pragma unroll
-          for (int r = 0; r < 9; ++r) Kout[(int64_t)(r * 9 + col) * nv + v] = (KT)dP[r];
+          for (int b = 0; b < 12; ++b) z += x[b] * kSlipS[b][i] * kSlipM[b][j];
+          Z[3 * i + j] = z;
         }
-      }
+      double CeZ[9], CeZA[9], dE[9], dS[9];
+      mm3(k.Ce, Z, CeZ);
+      mm3(CeZ, k.Ainv, CeZA);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          dE[3 * i + j] = 0.5 * (av[i] * bv[j] + av[j] * bv[i]) - 0.5 * (CeZA[3 * i + j] + CeZA[3 * j + i]);
+      cubic_stress(p, dE, dS);
+      double t1[9], t2[9], dP[9];
+      mm3(Z, Q, t1);               // - Fe Z Q
+      mm3(k.Fe, t1, dP);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dP[i] = -dP[i];
+      mmt3(dS, G, t1);             // + Fe dS G^T
+      mm3(k.Fe, t1, t2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dP[i] += t2[i];
+      mm3(G, Z, t1);               // - W Z^T G^T = - W (G Z)^T
+      mmt3(W, t1, t2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];   // + e_k (x) H_l.
+      const int col = 3 * kk + ll;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) Kout[(int64_t)(r * 9 + col) * nv + v] = (KT)dP[r];
     }
   }
-  if (args.blk_stats) {
-    s_it[threadIdx.x] = my_it;
-    s_fail[threadIdx.x] = my_fail;
-    __syncthreads();
-    for (int s = 32; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        s_it[threadIdx.x] = max(s_it[threadIdx.x], s_it[threadIdx.x + s]);
-        s_fail[threadIdx.x] += s_fail[threadIdx.x + s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      args.blk_stats[2 * blockIdx.x] = s_it[0];
-      args.blk_stats[2 * blockIdx.x + 1] = s_fail[0];
-    }
-  }
-  if (args.iters && v < nv) args.iters[v] = my_fail ? -my_it - 1 : my_it;
 }
 
 // Commit of an increment: Fp = (R A_c R^T) Fp_n and rho_SSD = rho_SSD,n + h |dg| (eq. 8),
@@ -453,13 +493,20 @@ __global__ void k_rotate_tangent(int64_t nv, const int32_t* gid, const double* g
   }
 }
 
-void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st) {
+void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st) {
   const int bs = 64;
   const int64_t nb = (a.nvox + bs - 1) / bs;
-  if (fp32_tangent)
-    hipLaunchKernelGGL(k_constitutive<float>, dim3((unsigned)nb), dim3(bs), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_constitutive<double>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+  const int nb_slow = (int)std::min<int64_t>(nb, 4096);
+  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, st, a.stats);
+  if (fp32) {
+    hipLaunchKernelGGL(k_slip_fast<true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL(k_slip_slow<true>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL((k_stress_tangent<float, true>), dim3((unsigned)nb), dim3(bs), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_slip_fast<false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL(k_slip_slow<false>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL((k_stress_tangent<double, false>), dim3((unsigned)nb), dim3(bs), 0, st, a);
+  }
 }
 
 void launch_commit(const CommitArgs& a, hipStream_t st) {

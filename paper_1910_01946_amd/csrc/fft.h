@@ -167,4 +167,11 @@ __device__ void fft_lines(cplx<T>* buf, const LineLayout& L, const AxisPlan& ap,
   }
 }
 
+// Copy a twiddle table (n entries) into LDS; the caller synchronises before use.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cplx<T>* dst, const void* src, int n) {
+  const cplx<T>* s = reinterpret_cast<const cplx<T>*>(src);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = s[i];
+}
+
 }  // namespace rve

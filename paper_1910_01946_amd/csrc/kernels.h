@@ -34,7 +34,8 @@ struct ConstArgs {
   double* P;
   void* K;                       // crystal-frame tangent (double or float), may be null
   double dt;
-  int32_t* blk_stats;            // per block {max local iterations, failures}, may be null
+  int32_t* stats;                // device {max local iterations, failures, work-list length, -}
+  int32_t* work;                 // device work list, nvox entries
   int32_t* iters;                // per voxel local iterations (negative: failed), may be null
 };
 

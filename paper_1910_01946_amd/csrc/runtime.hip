@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <memory>
+#include <thread>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -318,8 +320,16 @@ struct Work {
   bool fp32 = false;
   bool ready = false;
   Plan plan;
-  DevBuf K, xa, xb, r, p, q, spec;
+  DevBuf K, xa, xb, r, p, q, y, spec;
+  bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
 };
+
+// RVE_PLANE=0 in the environment selects the three-pass (x, y, z) spectral kernels even
+// where the plane kernels fit (both are kept and tested).
+static bool plane_enabled() {
+  const char* e = std::getenv("RVE_PLANE");
+  return !(e && e[0] == '0');
+}
 
 struct RVE {
   Work w[2];     // [0] FP64, [1] FP32 (allocated on first use)
@@ -335,6 +345,12 @@ struct RVE {
   // work
   DevBuf F_work, F_try, P_work, dg_saved, cg, partial, blk;
   int64_t fp64_fallbacks = 0;
+  hipStream_t stream = nullptr;   // each RVE runs on its own stream
+  CGState* host_cg = nullptr;     // pinned copy of the CG scalars
+  ~RVE() {
+    if (host_cg) (void)hipHostFree(host_cg);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
   bool have_prev = false;
   double Favg[9], Favg_prev[9], Pavg[9];
   double Fbar_prev[9];
@@ -344,11 +360,11 @@ struct RVE {
 struct Ctx {
   int device = 0;
   bool fp32 = false;
+  int workers = 8;               // host threads driving RVEs concurrently
   rve_options opt;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // caller's stream (optional)
   bool own_stream = false;
   std::vector<std::unique_ptr<RVE>> rves;
-  CGState* host_cg = nullptr;  // pinned
 };
 
 static void upload(DevBuf& b, const void* src, size_t bytes) {
@@ -370,8 +386,10 @@ static Work& work(RVE& R, bool fp32) {
     w.p.alloc(ts * 9 * nv);
     w.q.alloc(ts * 9 * nv);
     w.spec.alloc(ts * 2 * 9 * w.plan.g.nspec);
+    w.y.alloc(ts * 9 * nv);
     w.ready = true;
   }
+  w.plane = plane_enabled() && plane_fits(w.plan.g, fp32);
   return w;
 }
 
@@ -418,12 +436,14 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   R.F_try.alloc(f9);
   R.P_work.alloc(f9);
   R.dg_saved.alloc(f12);
+  HIPCHECK(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));
+  HIPCHECK(hipHostMalloc((void**)&R.host_cg, sizeof(CGState), hipHostMallocDefault));
   Work& w = work(R, C.fp32);
   R.cg.alloc(sizeof(CGState));
   HIPCHECK(hipMemset(R.cg.p, 0, sizeof(CGState)));
-  const int nb = std::max(xfwd_blocks(w.plan.g), 1024);
+  const int nb = std::max(std::max(xfwd_blocks(w.plan.g), 1024), std::max(9 * R.n[2], 2048));
   R.partial.alloc(sizeof(double) * 12 * nb);  // >= 3 x blocks of the x passes, 12 x colsum blocks
-  R.blk.alloc(sizeof(int32_t) * 2 * ((nv + 63) / 64));
+  R.blk.alloc(sizeof(int32_t) * (4 + nv));     // local-solve counters and work list
   for (int i = 0; i < 9; ++i) {
     R.Favg[i] = R.Favg_prev[i] = R.Fbar_prev[i] = (i % 4 == 0) ? 1.0 : 0.0;
     R.Pavg[i] = 0.0;
@@ -457,18 +477,16 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.P = R.P_work.as<double>();
   a.K = tangent ? w.K.p : nullptr;
   a.dt = dt;
-  a.blk_stats = R.blk.as<int32_t>();
-  launch_constitutive(a, w.fp32, C.stream);
+  a.stats = R.blk.as<int32_t>();
+  a.work = R.blk.as<int32_t>() + 4;
+  launch_constitutive(a, w.fp32, R.stream);
   check_launch("constitutive");
-  const int64_t nb = (R.nvox + 63) / 64;
-  std::vector<int32_t> st(2 * nb);
-  HIPCHECK(hipMemcpyAsync(st.data(), R.blk.p, sizeof(int32_t) * 2 * nb, hipMemcpyDeviceToHost, C.stream));
-  HIPCHECK(hipStreamSynchronize(C.stream));
+  int32_t st4[4];
+  HIPCHECK(hipMemcpyAsync(st4, R.blk.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, R.stream));
+  HIPCHECK(hipStreamSynchronize(R.stream));
   LocalStats ls;
-  for (int64_t b = 0; b < nb; ++b) {
-    ls.max_iters = std::max(ls.max_iters, st[2 * b]);
-    ls.failures += st[2 * b + 1];
-  }
+  ls.max_iters = st4[0];
+  ls.failures = st4[1];
   return ls;
 }
 
@@ -476,13 +494,41 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
 static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const double* mask_keep, const double* target,
                            void* x_zero) {
   const GridPlan& g = w.plan.g;
+  if (w.plane) {
+    PlaneArgs pa{PF_F64, P64, w.spec.p};
+    launch_plane_fwd(g, w.fp32, pa, nullptr, R.stream);
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_GREEN;
+    m.spec = w.spec.p;
+    for (int c = 0; c < 9; ++c) {
+      m.mask_keep[c] = mask_keep[c];
+      m.dc_target[c] = target ? target[c] : 0.0;
+    }
+    m.inv_n = 1.0 / (double)g.nvox;
+    launch_mid(g, w.fp32, m, R.stream);
+    PlaneInvArgs pi;
+    std::memset(&pi, 0, sizeof(pi));
+    pi.mode = PI_RESID;
+    pi.spec = w.spec.p;
+    pi.x = x_zero;
+    pi.r = w.r.p;
+    pi.p = w.p.p;
+    pi.partial = R.partial.as<double>();
+    launch_plane_inv(g, w.fp32, pi, R.stream);
+    launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), plane_blocks(g), 0.0, 0, R.stream);
+    check_launch("residual");
+    HIPCHECK(hipMemcpyAsync(R.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
+    HIPCHECK(hipStreamSynchronize(R.stream));
+    return R.host_cg->rr;
+  }
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
   xf.mode = XF_FIELD64;
   xf.in64 = P64;
   xf.spec = w.spec.p;
-  launch_xfwd(g, w.fp32, xf, C.stream);
-  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, C.stream);
+  launch_xfwd(g, w.fp32, xf, R.stream);
+  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, R.stream);
   MidArgs m;
   std::memset(&m, 0, sizeof(m));
   m.op = MID_GREEN;
@@ -492,8 +538,8 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
     m.dc_target[c] = target ? target[c] : 0.0;
   }
   m.inv_n = 1.0 / (double)g.nvox;
-  launch_mid(g, w.fp32, m, C.stream);
-  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, C.stream);
+  launch_mid(g, w.fp32, m, R.stream);
+  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, R.stream);
   XInvArgs xi;
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_RESID;
@@ -502,12 +548,12 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
   xi.r = w.r.p;
   xi.p = w.p.p;
   xi.partial = R.partial.as<double>();
-  launch_xinv(g, w.fp32, xi, C.stream);
-  launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), xinv_blocks(g), 0.0, 0, C.stream);
+  launch_xinv(g, w.fp32, xi, R.stream);
+  launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), xinv_blocks(g), 0.0, 0, R.stream);
   check_launch("residual");
-  HIPCHECK(hipMemcpyAsync(C.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
-  HIPCHECK(hipStreamSynchronize(C.stream));
-  return C.host_cg->rr;
+  HIPCHECK(hipMemcpyAsync(R.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
+  HIPCHECK(hipStreamSynchronize(R.stream));
+  return R.host_cg->rr;
 }
 
 // conjugate gradients on G(K : x) = r (x, r, p set by run_residual); returns iterations
@@ -518,13 +564,13 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   const int nb = xfwd_blocks(g);
   // restart the CG bookkeeping from the residual just computed
   {
-    CGState s = *C.host_cg;
+    CGState s = *R.host_cg;
     s.iter = 0;
     s.done = (s.rr0 > 0.0 && C.opt.max_cg > 0) ? 0 : 1;
     s.tol2 = C.opt.cg_tol * C.opt.cg_tol;
     s.max_iter = C.opt.max_cg;
-    *C.host_cg = s;
-    HIPCHECK(hipMemcpyAsync(cg, C.host_cg, sizeof(CGState), hipMemcpyHostToDevice, C.stream));
+    *R.host_cg = s;
+    HIPCHECK(hipMemcpyAsync(cg, R.host_cg, sizeof(CGState), hipMemcpyHostToDevice, R.stream));
   }
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
@@ -555,41 +601,71 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   xi.q = w.q.p;
   xi.cg = cg;
   xi.partial = part;
+  PrepArgs pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.K = w.K.p;
+  pr.gid = R.d_gid.as<int32_t>();
+  pr.grainR = R.d_R.as<double>();
+  pr.x = x;
+  pr.r = w.r.p;
+  pr.p = w.p.p;
+  pr.q = w.q.p;
+  pr.y = w.y.p;
+  pr.cg = cg;
+  pr.partial = part;
+  PlaneArgs pa{PF_T, w.y.p, w.spec.p};
+  PlaneInvArgs pi;
+  std::memset(&pi, 0, sizeof(pi));
+  pi.mode = PI_CG;
+  pi.spec = w.spec.p;
+  pi.r = w.r.p;
+  pi.p = w.p.p;
+  pi.q = w.q.p;
+  pi.cg = cg;
+  pi.partial = part + 2048;
   const int chunk = 4;
   for (;;) {
-    if (C.host_cg->done) break;
-    for (int i = 0; i < chunk; ++i) {
-      launch_xfwd(g, w.fp32, xf, C.stream);
-      launch_cg_beta(cg, part, nb, C.stream);
-      launch_yfft(g, w.fp32, w.spec.p, -1, cg, C.stream);
-      launch_mid(g, w.fp32, m, C.stream);
-      launch_yfft(g, w.fp32, w.spec.p, +1, cg, C.stream);
-      launch_xinv(g, w.fp32, xi, C.stream);
-      launch_cg_alpha(cg, part, nb, C.stream);
+    if (R.host_cg->done) break;
+    for (int i = 0; i < chunk && w.plane; ++i) {
+      launch_cg_prep(g, w.fp32, pr, R.stream);
+      launch_cg_beta(cg, part, prep_blocks(g), R.stream);
+      launch_plane_fwd(g, w.fp32, pa, cg, R.stream);
+      launch_mid(g, w.fp32, m, R.stream);
+      launch_plane_inv(g, w.fp32, pi, R.stream);
+      launch_cg_alpha(cg, part + 2048, plane_blocks(g), R.stream);
+    }
+    for (int i = 0; i < chunk && !w.plane; ++i) {
+      launch_xfwd(g, w.fp32, xf, R.stream);
+      launch_cg_beta(cg, part, nb, R.stream);
+      launch_yfft(g, w.fp32, w.spec.p, -1, cg, R.stream);
+      launch_mid(g, w.fp32, m, R.stream);
+      launch_yfft(g, w.fp32, w.spec.p, +1, cg, R.stream);
+      launch_xinv(g, w.fp32, xi, R.stream);
+      launch_cg_alpha(cg, part, nb, R.stream);
     }
     check_launch("cg");
-    HIPCHECK(hipMemcpyAsync(C.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, C.stream));
-    HIPCHECK(hipStreamSynchronize(C.stream));
+    HIPCHECK(hipMemcpyAsync(R.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
+    HIPCHECK(hipStreamSynchronize(R.stream));
   }
-  done_code = C.host_cg->done;
-  return C.host_cg->iter;
+  done_code = R.host_cg->done;
+  return R.host_cg->iter;
 }
 
 static double rms_of(Ctx& C, RVE& R, Work& w, const void* f, int64_t n) {
-  const int nb = launch_sumsq(f, w.fp32, n, R.partial.as<double>(), C.stream);
+  const int nb = launch_sumsq(f, w.fp32, n, R.partial.as<double>(), R.stream);
   std::vector<double> part(nb);
-  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * nb, hipMemcpyDeviceToHost, C.stream));
-  HIPCHECK(hipStreamSynchronize(C.stream));
+  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * nb, hipMemcpyDeviceToHost, R.stream));
+  HIPCHECK(hipStreamSynchronize(R.stream));
   double s = 0.0;
   for (double v : part) s += v;
   return std::sqrt(s / (double)n);
 }
 
 static void field_average(Ctx& C, RVE& R, const double* f, int ncomp, double* out) {
-  const int nb = launch_colsum(f, ncomp, R.nvox, R.partial.as<double>(), C.stream);
+  const int nb = launch_colsum(f, ncomp, R.nvox, R.partial.as<double>(), R.stream);
   std::vector<double> part((size_t)nb * ncomp);
-  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, C.stream));
-  HIPCHECK(hipStreamSynchronize(C.stream));
+  HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, R.stream));
+  HIPCHECK(hipStreamSynchronize(R.stream));
   for (int c = 0; c < ncomp; ++c) {
     double s = 0.0;
     for (int b = 0; b < nb; ++b) s += part[(size_t)b * ncomp + c];
@@ -599,21 +675,42 @@ static void field_average(Ctx& C, RVE& R, const double* f, int ncomp, double* ou
 
 static void run_nye(Ctx& C, RVE& R, Work& w) {
   const GridPlan& g = w.plan.g;
+  if (w.plane) {
+    PlaneArgs pa{PF_FPI, R.Fp.as<double>(), w.spec.p};
+    launch_plane_fwd(g, w.fp32, pa, nullptr, R.stream);
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_CURL;
+    m.spec = w.spec.p;
+    m.inv_n = 1.0 / (double)g.nvox;
+    m.inv_h = 1.0 / R.h;
+    launch_mid(g, w.fp32, m, R.stream);
+    PlaneInvArgs pi;
+    std::memset(&pi, 0, sizeof(pi));
+    pi.mode = PI_OUT64;
+    pi.spec = w.spec.p;
+    pi.out64 = R.nye.as<double>();
+    launch_plane_inv(g, w.fp32, pi, R.stream);
+    launch_gnd(R.nvox, R.nye.as<double>(), R.d_gid.as<int32_t>(), R.d_R.as<double>(), R.d_mat.as<MatDev>(),
+               R.rho_gnd.as<double>(), R.stream);
+    check_launch("nye");
+    return;
+  }
   XFwdArgs xf;
   std::memset(&xf, 0, sizeof(xf));
   xf.mode = XF_FP_MINUS_I;
   xf.in64 = R.Fp.as<double>();
   xf.spec = w.spec.p;
-  launch_xfwd(g, w.fp32, xf, C.stream);
-  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, C.stream);
+  launch_xfwd(g, w.fp32, xf, R.stream);
+  launch_yfft(g, w.fp32, w.spec.p, -1, nullptr, R.stream);
   MidArgs m;
   std::memset(&m, 0, sizeof(m));
   m.op = MID_CURL;
   m.spec = w.spec.p;
   m.inv_n = 1.0 / (double)g.nvox;
   m.inv_h = 1.0 / R.h;
-  launch_mid(g, w.fp32, m, C.stream);
-  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, C.stream);
+  launch_mid(g, w.fp32, m, R.stream);
+  launch_yfft(g, w.fp32, w.spec.p, +1, nullptr, R.stream);
   XInvArgs xi;
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_NYE;
@@ -623,7 +720,7 @@ static void run_nye(Ctx& C, RVE& R, Work& w) {
   xi.gid = R.d_gid.as<int32_t>();
   xi.grainR = R.d_R.as<double>();
   xi.mat = R.d_mat.as<MatDev>();
-  launch_xinv(g, w.fp32, xi, C.stream);
+  launch_xinv(g, w.fp32, xi, R.stream);
   check_launch("nye");
 }
 
@@ -649,10 +746,14 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
   double rr = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, x);
   st.residual_evals++;
   double res = std::sqrt(rr / n9);
+  if (!std::isfinite(res)) {
+    *why = "non-finite residual at the initial guess";
+    return RVE_ENOCONV;
+  }
   for (int it = 0; it < C.opt.max_newton; ++it) {
     int done = 0;
     const int ncg = run_cg(C, R, w, x, keep, done);
-    const CGState cg_end = *C.host_cg;
+    const CGState cg_end = *R.host_cg;
     st.cg_iters += ncg;
     // A breakdown (negative curvature along p), a diverging residual or the iteration cap
     // ends CG with its current iterate, as truncated CG does; the residual line search
@@ -672,7 +773,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
         const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
         st.residual_evals++;
         res_try = std::sqrt(rr_t / n9);
-        if (res_try <= res || lam * dF <= C.opt.newton_tol) {
+        if (std::isfinite(res_try) && (res_try <= res || lam * dF <= C.opt.newton_tol)) {
           accepted = true;
           break;
         }
@@ -712,9 +813,9 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   const int64_t nv = R.nvox;
   double keep[9];
   for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
-  HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+  HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, R.stream));
   auto restore_dg = [&]() {
-    HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, C.stream));
+    HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, R.stream));
   };
   const char* why = "";
   auto attempt = [&](Work& w, int max_stages) -> int32_t {
@@ -726,7 +827,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
       cr.v[c] = mask[c] ? (dmac - dprev) : 0.0;
     }
     launch_predictor(R.F.as<double>(), R.have_prev ? R.F_prev.as<double>() : nullptr, cr, R.F_work.as<double>(),
-                     nv, C.stream);
+                     nv, R.stream);
     check_launch("predictor");
     int32_t rc = newton_solve(C, R, w, keep, Pbar, dt, st, &why);
     for (int m = 2; rc != RVE_OK && m <= max_stages; m *= 2) {
@@ -734,7 +835,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
       restore_dg();
       Corr9 zero;
       for (int c = 0; c < 9; ++c) zero.v[c] = 0.0;
-      launch_predictor(R.F.as<double>(), nullptr, zero, R.F_work.as<double>(), nv, C.stream);
+      launch_predictor(R.F.as<double>(), nullptr, zero, R.F_work.as<double>(), nv, R.stream);
       double Fb_prev[9];
       std::memcpy(Fb_prev, R.Fbar_prev, sizeof(Fb_prev));
       rc = RVE_OK;
@@ -746,7 +847,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
           step.v[c] = mask[c] ? (target - Fb_prev[c]) : 0.0;
           Fb_prev[c] = target;
         }
-        launch_predictor(R.F_work.as<double>(), nullptr, step, R.F_work.as<double>(), nv, C.stream);
+        launch_predictor(R.F_work.as<double>(), nullptr, step, R.F_work.as<double>(), nv, R.stream);
         check_launch("predictor");
         rc = newton_solve(C, R, w, keep, Pbar, dt, st, &why);
       }
@@ -766,7 +867,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   }
   if (rc != RVE_OK) {
     restore_dg();
-    HIPCHECK(hipStreamSynchronize(C.stream));
+    HIPCHECK(hipStreamSynchronize(R.stream));
     st.status = rc;
     g_last_error = why;
     return rc;
@@ -781,7 +882,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   ca.Fp = R.Fp.as<double>();
   ca.rho_ssd = R.rho_ssd.as<double>();
   ca.rho_gnd = R.rho_gnd.as<double>();
-  launch_commit(ca, C.stream);
+  launch_commit(ca, R.stream);
   check_launch("commit");
   std::swap(R.F_prev.p, R.F.p);     // F_prev <- F_{k-1}
   std::swap(R.F.p, R.F_work.p);     // F <- F_k
@@ -843,13 +944,8 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
     C->fp32 = o.precision == RVE_MIXED;
     C->device = o.device;
     HIPCHECK(hipSetDevice(C->device));
-    if (o.stream) {
-      C->stream = (hipStream_t)o.stream;
-    } else {
-      HIPCHECK(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking));
-      C->own_stream = true;
-    }
-    HIPCHECK(hipHostMalloc((void**)&C->host_cg, sizeof(CGState), hipHostMallocDefault));
+    C->stream = (hipStream_t)o.stream;
+    if (const char* e = std::getenv("RVE_WORKERS")) C->workers = std::max(1, std::atoi(e));
     for (int i = 0; i < n_rve; ++i) {
       C->rves.emplace_back(new RVE());
       init_rve(*C, *C->rves.back(), descs[i]);
@@ -862,10 +958,8 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
 void rve_destroy(rve_handle h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
-  (void)hipStreamSynchronize(h->stream);
+  for (auto& r : h->rves) (void)hipStreamSynchronize(r->stream);
   h->rves.clear();
-  if (h->host_cg) (void)hipHostFree(h->host_cg);
-  if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 
@@ -883,17 +977,57 @@ int32_t rve_step_increment(rve_handle h, const double* F_bar, const uint8_t* mas
     HIPCHECK(hipSetDevice(h->device));
     std::vector<double> zeros(9 * (size_t)nr, 0.0);
     const double* Pb = P_bar ? P_bar : zeros.data();
+    // work queued on the caller's stream comes first
+    if (h->stream) {
+      hipEvent_t ev;
+      HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHECK(hipEventRecord(ev, h->stream));
+      for (auto& r : h->rves) HIPCHECK(hipStreamWaitEvent(r->stream, ev, 0));
+      HIPCHECK(hipEventDestroy(ev));
+    }
+    // RVEs are independent: host workers drive them concurrently, one stream each, so
+    // that small grids share the GPU (the host loop of one RVE synchronises on its own
+    // stream only).
+    std::vector<rve_step_stats> st(nr);
+    std::vector<int32_t> rcs(nr, RVE_OK);
+    std::vector<std::string> msgs(nr);
+    std::atomic<int> next(0);
+    auto worker = [&]() {
+      (void)hipSetDevice(h->device);
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= nr) break;
+        try {
+          rcs[i] = step_rve(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, st[i]);
+          if (rcs[i] != RVE_OK) msgs[i] = g_last_error;
+        } catch (const Error& e) {
+          rcs[i] = e.code;
+          msgs[i] = e.what();
+          st[i].status = e.code;
+        } catch (const std::exception& e) {
+          rcs[i] = RVE_EDEVICE;
+          msgs[i] = e.what();
+          st[i].status = RVE_EDEVICE;
+        }
+      }
+    };
+    const int nw = std::max(1, std::min(nr, h->workers));
+    if (nw == 1) {
+      worker();
+    } else {
+      std::vector<std::thread> pool;
+      for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
+      for (auto& t : pool) t.join();
+    }
+    if (stats)
+      for (int i = 0; i < nr; ++i) stats[i] = st[i];
     int32_t worst = RVE_OK;
     std::string msg;
-    for (int i = 0; i < nr; ++i) {
-      rve_step_stats s;
-      const int32_t rc = step_rve(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, s);
-      if (stats) stats[i] = s;
-      if (rc != RVE_OK) {
-        worst = rc;
-        msg = "rve " + std::to_string(i) + ": " + g_last_error;
+    for (int i = 0; i < nr; ++i)
+      if (rcs[i] != RVE_OK) {
+        worst = rcs[i];
+        msg = "rve " + std::to_string(i) + ": " + msgs[i];
       }
-    }
     if (worst != RVE_OK) throw Error(worst, msg);
     return RVE_OK;
   });
@@ -937,8 +1071,8 @@ int32_t rve_get_field(rve_handle h, int32_t rve, int32_t which, double* out) {
       default: throw Error(RVE_EINVAL, "unknown field");
     }
     HIPCHECK(hipSetDevice(h->device));
-    HIPCHECK(hipMemcpyAsync(out, b->p, sizeof(double) * nc * R.nvox, hipMemcpyDeviceToHost, h->stream));
-    HIPCHECK(hipStreamSynchronize(h->stream));
+    HIPCHECK(hipMemcpyAsync(out, b->p, sizeof(double) * nc * R.nvox, hipMemcpyDeviceToHost, R.stream));
+    HIPCHECK(hipStreamSynchronize(R.stream));
     return RVE_OK;
   });
 }
@@ -970,7 +1104,7 @@ int32_t rve_save_state(rve_handle h, void* buf) {
       const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
       for (int i = 0; i < 8; ++i) {
         const size_t n = sizeof(double) * nc[i] * R.nvox;
-        HIPCHECK(hipMemcpyAsync(o, bufs[i]->p, n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(hipMemcpyAsync(o, bufs[i]->p, n, hipMemcpyDeviceToHost, R.stream));
         o += n;
       }
       double sc[40] = {0};
@@ -982,8 +1116,8 @@ int32_t rve_save_state(rve_handle h, void* buf) {
       sc[37] = (double)R.increments;
       std::memcpy(o, sc, sizeof(sc));
       o += sizeof(sc);
+      HIPCHECK(hipStreamSynchronize(R.stream));
     }
-    HIPCHECK(hipStreamSynchronize(h->stream));
     return RVE_OK;
   });
 }
@@ -999,7 +1133,7 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
       const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
       for (int i = 0; i < 8; ++i) {
         const size_t n = sizeof(double) * nc[i] * R.nvox;
-        HIPCHECK(hipMemcpyAsync(bufs[i]->p, o, n, hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(hipMemcpyAsync(bufs[i]->p, o, n, hipMemcpyHostToDevice, R.stream));
         o += n;
       }
       double sc[40];
@@ -1011,8 +1145,8 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
       std::memcpy(R.Fbar_prev, sc + 27, 72);
       R.have_prev = sc[36] != 0.0;
       R.increments = (int64_t)sc[37];
+      HIPCHECK(hipStreamSynchronize(R.stream));
     }
-    HIPCHECK(hipStreamSynchronize(h->stream));
     return RVE_OK;
   });
 }
@@ -1032,7 +1166,8 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
     MatDev md = make_material(*mat);
     std::vector<double> Rg(9 * (size_t)n_grains);
     for (int g = 0; g < n_grains; ++g) quat_to_R(grain_quat + 4 * g, &Rg[9 * g]);
-    DevBuf dmat, dR, Kc;
+    DevBuf dmat, dR, Kc, cnt;
+    cnt.alloc(sizeof(int32_t) * (4 + nvox));
     upload(dmat, &md, sizeof(md));
     upload(dR, Rg.data(), sizeof(double) * Rg.size());
     if (K) Kc.alloc(sizeof(double) * 81 * nvox);
@@ -1051,6 +1186,8 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
     a.K = K ? Kc.p : nullptr;
     a.dt = dt;
     a.iters = iters;
+    a.stats = cnt.as<int32_t>();
+    a.work = cnt.as<int32_t>() + 4;
     launch_constitutive(a, false, st);
     check_launch("constitutive");
     if (K) {
@@ -1073,13 +1210,19 @@ int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, cons
     const GridPlan& g = P.g;
     DevBuf spec;
     spec.alloc(tsize(fp32) * 2 * 9 * g.nspec);
+    const bool plane = plane_enabled() && plane_fits(g, fp32);
     XFwdArgs xf;
     std::memset(&xf, 0, sizeof(xf));
     xf.mode = XF_FIELD64;
     xf.in64 = A;
     xf.spec = spec.p;
-    launch_xfwd(g, fp32, xf, st);
-    launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    if (plane) {
+      PlaneArgs pa{PF_F64, A, spec.p};
+      launch_plane_fwd(g, fp32, pa, nullptr, st);
+    } else {
+      launch_xfwd(g, fp32, xf, st);
+      launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    }
     MidArgs m;
     std::memset(&m, 0, sizeof(m));
     m.op = MID_GREEN;
@@ -1090,13 +1233,22 @@ int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, cons
     }
     m.inv_n = 1.0 / (double)g.nvox;
     launch_mid(g, fp32, m, st);
-    launch_yfft(g, fp32, spec.p, +1, nullptr, st);
-    XInvArgs xi;
-    std::memset(&xi, 0, sizeof(xi));
-    xi.mode = XI_OUT64;
-    xi.spec = spec.p;
-    xi.out64 = out;
-    launch_xinv(g, fp32, xi, st);
+    if (plane) {
+      PlaneInvArgs pi;
+      std::memset(&pi, 0, sizeof(pi));
+      pi.mode = PI_OUT64;
+      pi.spec = spec.p;
+      pi.out64 = out;
+      launch_plane_inv(g, fp32, pi, st);
+    } else {
+      launch_yfft(g, fp32, spec.p, +1, nullptr, st);
+      XInvArgs xi;
+      std::memset(&xi, 0, sizeof(xi));
+      xi.mode = XI_OUT64;
+      xi.spec = spec.p;
+      xi.out64 = out;
+      launch_xinv(g, fp32, xi, st);
+    }
     check_launch("project");
     HIPCHECK(hipStreamSynchronize(st));
     return RVE_OK;
@@ -1128,13 +1280,19 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
       upload(dmat, &md, sizeof(md));
       upload(dR, Rg.data(), sizeof(double) * Rg.size());
     }
-    XFwdArgs xf;
-    std::memset(&xf, 0, sizeof(xf));
-    xf.mode = XF_FP_MINUS_I;
-    xf.in64 = Fp;
-    xf.spec = spec.p;
-    launch_xfwd(g, fp32, xf, st);
-    launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    const bool plane = plane_enabled() && plane_fits(g, fp32);
+    if (plane) {
+      PlaneArgs pa{PF_FPI, Fp, spec.p};
+      launch_plane_fwd(g, fp32, pa, nullptr, st);
+    } else {
+      XFwdArgs xf;
+      std::memset(&xf, 0, sizeof(xf));
+      xf.mode = XF_FP_MINUS_I;
+      xf.in64 = Fp;
+      xf.spec = spec.p;
+      launch_xfwd(g, fp32, xf, st);
+      launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    }
     MidArgs m;
     std::memset(&m, 0, sizeof(m));
     m.op = MID_CURL;
@@ -1142,6 +1300,18 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
     m.inv_n = 1.0 / (double)g.nvox;
     m.inv_h = 1.0 / h;
     launch_mid(g, fp32, m, st);
+    if (plane) {
+      PlaneInvArgs pi;
+      std::memset(&pi, 0, sizeof(pi));
+      pi.mode = PI_OUT64;
+      pi.spec = spec.p;
+      pi.out64 = nye;
+      launch_plane_inv(g, fp32, pi, st);
+      if (gnd) launch_gnd(g.nvox, nye, gid, dR.as<double>(), dmat.as<MatDev>(), rho_gnd, st);
+      check_launch("curl");
+      HIPCHECK(hipStreamSynchronize(st));
+      return RVE_OK;
+    }
     launch_yfft(g, fp32, spec.p, +1, nullptr, st);
     XInvArgs xi;
     std::memset(&xi, 0, sizeof(xi));

@@ -108,6 +108,50 @@ void launch_cg_start(CGState* cg, const double* partial, int n, double tol2, int
 int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hipStream_t st);
 int launch_sumsq(const void* f, bool fp32, int64_t n, double* partial, hipStream_t st);
 
+// ---- plane path (x and y transforms of one component plane in LDS) ----------------
+enum PlaneSrc { PF_T = 0, PF_F64 = 1, PF_FPI = 2 };
+enum PlaneMode { PI_CG = 0, PI_RESID = 1, PI_OUT64 = 2 };
+
+struct PlaneArgs {
+  int src;                     // PF_T: field of type T; PF_F64: FP64 field; PF_FPI: FP64 Fp - I
+  const void* in;              // 9 x nvox
+  void* spec;                  // out: half spectrum
+};
+
+struct PlaneInvArgs {
+  int mode;
+  const void* spec;
+  void* x;                     // PI_RESID: set to 0
+  void* r;                     // PI_RESID: out (-w); PI_CG: in
+  void* p;                     // PI_RESID: out (= r); PI_CG: p = r + beta p
+  void* q;                     // PI_CG: q = w + beta q
+  double* out64;               // PI_OUT64
+  CGState* cg;
+  double* partial;             // per-block (9 x nz) r.r (PI_RESID) or p.q (PI_CG)
+};
+
+struct PrepArgs {
+  const void* K;               // crystal-frame tangent (T)
+  const int32_t* gid;
+  const double* grainR;
+  void* x;
+  void* r;
+  const void* p;
+  const void* q;
+  void* y;                     // out: K : r (T)
+  CGState* cg;
+  double* partial;             // per-block r.r
+};
+
+bool plane_fits(const GridPlan& g, bool fp32);
+int plane_blocks(const GridPlan& g);
+int prep_blocks(const GridPlan& g);
+void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CGState* cg, hipStream_t st);
+void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
+void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st);
+void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,
+                double* rho_gnd, hipStream_t st);
+
 // Initial guess of an increment: out = 2 F - F_prev + corr (F + corr when F_prev is null).
 struct Corr9 {
   double v[9];

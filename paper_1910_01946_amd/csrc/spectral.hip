@@ -17,6 +17,8 @@
 // update and residual norm, Nye tensor and GND densities, or plain output).
 #include "spectral.h"
 
+#include <mutex>
+
 namespace rve {
 
 namespace {
@@ -174,16 +176,35 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   const int ky = blockIdx.y, kx0 = blockIdx.x * tz;
   const int tid = threadIdx.x, nthr = blockDim.x;
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
+  cplx<T>* twz = buf + 9 * nz * tzp;
+  load_twiddles(twz, g.twz, nz);
   const int nload = 9 * nz * tz;
-  for (int idx = tid; idx < nload; idx += nthr) {
-    const int j = idx % tz, t = idx / tz;
-    const int zz = t % nz, c = t / nz;
-    buf[(c * nz + zz) * tzp + j] =
-        (kx0 + j < nxh) ? spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j] : cmk((T)0, (T)0);
+  // 8 independent loads in flight per thread before the LDS writes
+  for (int b0 = tid; b0 < nload; b0 += 8 * nthr) {
+    cplx<T> val[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b0 + u * nthr;
+      val[u] = cmk((T)0, (T)0);
+      if (idx < nload) {
+        const int j = idx % tz, t = idx / tz;
+        const int zz = t % nz, c = t / nz;
+        if (kx0 + j < nxh) val[u] = spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b0 + u * nthr;
+      if (idx < nload) {
+        const int j = idx % tz, t = idx / tz;
+        const int zz = t % nz, c = t / nz;
+        buf[(c * nz + zz) * tzp + j] = val[u];
+      }
+    }
   }
   __syncthreads();
   LineLayout L{9 * tz, tz, nz * tzp, 1, tzp};
-  fft_lines<T, 18>(buf, L, g.az, reinterpret_cast<const cplx<T>*>(g.twz), (T)-1);
+  fft_lines<T, 18>(buf, L, g.az, twz, (T)-1);
   const cplx<double>* Ex = reinterpret_cast<const cplx<double>*>(g.Ex);
   const cplx<double>* Ey = reinterpret_cast<const cplx<double>*>(g.Ey);
   const cplx<double>* Ez = reinterpret_cast<const cplx<double>*>(g.Ez);
@@ -249,7 +270,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     for (int c = 0; c < 9; ++c) buf[(c * nz + kz) * tzp + j] = cmk((T)out[c].x, (T)out[c].y);
   }
   __syncthreads();
-  fft_lines<T, 18>(buf, L, g.az, reinterpret_cast<const cplx<T>*>(g.twz), (T)1);
+  fft_lines<T, 18>(buf, L, g.az, twz, (T)1);
   for (int idx = tid; idx < nload; idx += nthr) {
     const int j = idx % tz, t = idx / tz;
     const int zz = t % nz, c = t / nz;
@@ -483,11 +504,15 @@ __global__ void k_predictor(const double* F, const double* F_prev, Corr9 corr, d
 // has 160 KiB of LDS per compute unit).
 template <typename K>
 static void allow_lds(K kernel, size_t bytes) {
+  static std::mutex mu;
   static size_t granted = 65536;
-  if (bytes > granted) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
-    granted = bytes;
+  if (bytes > 65536) {
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes > granted) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes);
+      granted = bytes;
+    }
   }
 }
 
@@ -531,7 +556,7 @@ void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGSta
 
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) {
   const dim3 grid((g.nxh + g.tz - 1) / g.tz, g.ny);
-  const size_t sh = (size_t)9 * g.nz * (g.tz + 1) * (fp32 ? 8 : 16);
+  const size_t sh = ((size_t)9 * g.nz * (g.tz + 1) + g.nz) * (fp32 ? 8 : 16);
   if (fp32) {
     if (a.op == MID_GREEN) {
       allow_lds(k_mid<float, MID_GREEN>, sh);

@@ -68,7 +68,10 @@ def test_constitutive_update_and_tangent(lib, amp, hard):
 @pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 4), (10, 12, 6), (16, 16, 16), (64, 64, 64),
                                    (40, 48, 24)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_projection_matches_oracle(lib, shape, precision):
+@pytest.mark.parametrize("plane", ["1", "0"])
+def test_projection_matches_oracle(lib, shape, precision, plane, monkeypatch):
+    """Both spectral paths: x/y plane kernels in LDS (default) and the three-pass kernels."""
+    monkeypatch.setenv("RVE_PLANE", plane)
     import torch
     nx, ny, nz = shape
     A = synth.random_field(3, (nz, ny, nx, 3, 3), -1e7, 1e7)
@@ -77,7 +80,7 @@ def test_projection_matches_oracle(lib, shape, precision):
     ref = spectral.project(A, mask, target)
     V = nx * ny * nz
     out = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
-    print(f"project shape={shape} precision={precision}", flush=True)
+    print(f"project shape={shape} precision={precision} plane={plane}", flush=True)
     lib.project(shape, cuda(to_abi(A.reshape(V, 3, 3))), mask, out, dc_target=target.reshape(9),
                 precision=precision)
     torch.cuda.synchronize()
@@ -87,7 +90,9 @@ def test_projection_matches_oracle(lib, shape, precision):
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (6, 10, 4), (32, 32, 32)])
-def test_curl_and_gnd_match_oracle(lib, shape):
+@pytest.mark.parametrize("plane", ["1", "0"])
+def test_curl_and_gnd_match_oracle(lib, shape, plane, monkeypatch):
+    monkeypatch.setenv("RVE_PLANE", plane)
     import torch
     nx, ny, nz = shape
     V = nx * ny * nz
@@ -97,7 +102,7 @@ def test_curl_and_gnd_match_oracle(lib, shape):
     alpha, seg, rho = onye.gnd_from_fp(Fp, h, rve.grain_of_voxel, rve.quats, 0.256e-9)
     nye = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
     rg = torch.zeros((12, V), dtype=torch.float64, device="cuda:0")
-    print(f"curl shape={shape}", flush=True)
+    print(f"curl shape={shape} plane={plane}", flush=True)
     lib.spectral_curl(shape, h, cuda(to_abi(Fp.reshape(V, 3, 3))), nye, gid=cuda(rve.grain_of_voxel.reshape(-1)),
                       quats=rve.quats, burgers=0.256e-9, rho_gnd=rg)
     torch.cuda.synchronize()

@@ -36,7 +36,9 @@ def _run_both(lib, rve, path, n_inc, precision=0, newton_tol=1e-11, cg_tol=1e-10
     return o, h, out
 
 
-def test_c1_small_fp64_matches_oracle(lib):
+@pytest.mark.parametrize("plane", ["1", "0"])
+def test_c1_small_fp64_matches_oracle(lib, plane, monkeypatch):
+    monkeypatch.setenv("RVE_PLANE", plane)
     rves, path = synth.workload("c1", n_override=8, n_inc_override=20)
     o, h, out = _run_both(lib, rves[0], path, 3)
     for Po, Pg, Fo, Fg in out:
