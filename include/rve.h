@@ -147,6 +147,33 @@ int64_t rve_state_bytes(rve_handle h);
 int32_t rve_save_state(rve_handle h, void* buf);
 int32_t rve_load_state(rve_handle h, const void* buf);
 
+/* ---- Measurement support ----
+ * Kernel families whose launches can be timed; bit f of a mask selects family f. */
+enum {
+  RVE_KF_SLIP_FAST = 0,      /* local Newton on the slip increments, first pass (eqs. 5-6)       */
+  RVE_KF_SLIP_SLOW = 1,      /* continuation pass over the voxels the first pass left            */
+  RVE_KF_STRESS_TANGENT = 2, /* stress (eq. 14) and consistent tangent dP/dF                      */
+  RVE_KF_CG_PREP = 3,        /* CG vector update, r.r and K : r (eq. 18)                          */
+  RVE_KF_PLANE_FWD = 4,      /* x and y forward FFTs of one component plane                      */
+  RVE_KF_MID = 5,            /* z FFTs and the Green operator of eq. 17 with its inverse z FFTs  */
+  RVE_KF_PLANE_INV = 6       /* y and x inverse FFTs and the CG epilogue                          */
+};
+
+/* While mask != 0, every launch of the selected families during rve_step_increment
+ * carries a pair of HIP events that the dispatch records at the kernel's start and end
+ * (AMD's extended launch, on the stream it is launched on); the kernel durations are
+ * accumulated per family.  Launches that a finished CG solve turns into no-ops are not
+ * counted.  Each call clears the accumulators; mask 0 stops timing.
+ * Errors: RVE_EINVAL (unknown family bit). */
+int32_t rve_timing_start(rve_handle h, uint32_t mask);
+
+/* Accumulated figures of one family since the last rve_timing_start, summed over the
+ * handle's RVEs: launches, total event-measured duration in ms, and units: the
+ * algorithmic bytes of those launches for the spectral families (every input read once,
+ * every output written once) or the voxels covered for the constitutive families.  Any
+ * output pointer may be NULL.  Errors: RVE_EINVAL (unknown family). */
+int32_t rve_timing_read(rve_handle h, int32_t family, int64_t* launches, double* total_ms, double* units);
+
 void rve_destroy(rve_handle h);
 
 /* Message of the last failing call on this thread ("" if none). */

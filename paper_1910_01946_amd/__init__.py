@@ -106,6 +106,23 @@ class Homogenizer:
         check(lib().rve_get_field(self.h, i, which, _dp(out)))
         return out
 
+    def timing_start(self, families=()):
+        """Time the launches of the named kernel families (see _lib.KERNEL_FAMILIES) with
+        HIP events from now on; an empty list stops timing.  Clears the accumulators."""
+        mask = 0
+        for f in families:
+            mask |= 1 << _lib.KERNEL_FAMILIES[f]
+        check(lib().rve_timing_start(self.h, mask))
+
+    def timing_read(self, family):
+        """(launches, total ms, units) of a family since timing_start; units are
+        algorithmic bytes for the spectral families, voxels for the constitutive ones."""
+        n = C.c_int64(0)
+        t = C.c_double(0.0)
+        u = C.c_double(0.0)
+        check(lib().rve_timing_read(self.h, _lib.KERNEL_FAMILIES[family], C.byref(n), C.byref(t), C.byref(u)))
+        return n.value, t.value, u.value
+
     def save_state(self):
         nb = lib().rve_state_bytes(self.h)
         buf = np.zeros(nb, dtype=np.uint8)

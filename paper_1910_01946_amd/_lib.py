@@ -58,6 +58,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise LibraryMissing(f"{LIB_PATH} not found: build it with __graft_entry__.build() "
                              "(or python paper_1910_01946_amd/build.py)")
+    # torch brings its own HIP runtime; loading it first makes the library bind to that
+    # same runtime instead of initialising a second one in the process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     vp = C.c_void_p
@@ -90,6 +96,10 @@ def lib():
     L.rve_spectral_curl.argtypes = [P(C.c_int32), C.c_int32, C.c_double, vp, vp, vp, C.c_int32, dp,
                                     C.c_double, vp, vp]
     L.rve_spectral_curl.restype = C.c_int32
+    L.rve_timing_start.argtypes = [vp, C.c_uint32]
+    L.rve_timing_start.restype = C.c_int32
+    L.rve_timing_read.argtypes = [vp, C.c_int32, P(C.c_int64), dp, dp]
+    L.rve_timing_read.restype = C.c_int32
     _lib = L
     return L
 
@@ -97,7 +107,12 @@ def lib():
 # names the C ABI exports (checked by the CPU test suite)
 EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress", "rve_get_field",
            "rve_state_bytes", "rve_save_state", "rve_load_state", "rve_destroy", "rve_last_error",
-           "rve_constitutive_batch", "rve_project", "rve_spectral_curl"]
+           "rve_constitutive_batch", "rve_project", "rve_spectral_curl", "rve_timing_start",
+           "rve_timing_read"]
+
+# kernel families of rve_timing_start / rve_timing_read
+KERNEL_FAMILIES = {"slip_fast": 0, "slip_slow": 1, "stress_tangent": 2, "cg_prep": 3, "plane_fwd": 4, "mid": 5,
+                   "plane_inv": 6}
 
 
 class RVEError(RuntimeError):

@@ -267,9 +267,12 @@ __device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev&
 }
 
 // Local solve, pass 1: Newton at n = 1/m from the warm start, at most kFastIters steps.
-// Converged voxels write their slip increments; the others are appended to a work list
-// (their warm start stays in memory) for the continuation pass, so that a few stiff
-// voxels do not hold whole wavefronts.  stats[0] = largest iteration count (atomic max),
+// With args.predict the start is moved along the linearised response of the previous
+// converged evaluation (its slip sensitivity times the change of F): a low critical stress
+// makes the power law so steep that a change of F of a few yield strains leaves the
+// unmoved start far outside Newton's basin.  Converged voxels write their slip increments;
+// the others are appended to a work list (their unmoved warm start stays in memory) for
+// the continuation pass, so that a few stiff voxels do not hold whole wavefronts.  stats[0] = largest iteration count (atomic max),
 // stats[1] = failures, stats[2] = length of the work list.
 constexpr int kFastIters = 12;
 
@@ -285,6 +288,24 @@ __global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
   double dg[12];
 #pragma unroll
   for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+  if (args.predict) {
+    // first-order start along the Newton direction: the slip increments respond to a
+    // change of F with the sensitivity stored at the last converged evaluation
+    double dFs[9], dFc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      dFs[i] = DF32 ? (double)reinterpret_cast<const float*>(args.dF)[i * nv + v]
+                    : reinterpret_cast<const double*>(args.dF)[i * nv + v];
+    to_crystal(Rg, dFs, dFc);
+    const double s = args.lam - args.lam_base;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) d += (double)args.dgdF[(int64_t)(9 * a + c) * nv + v] * dFc[c];
+      dg[a] += s * d;
+    }
+  }
   int it = 0;
   const int ok = newton(p, M.n_exp, 1e-10, kFastIters, dg, it);
   if (ok) {
@@ -383,6 +404,10 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
 #pragma unroll
       for (int a = 0; a < 12; ++a) x[a] = D[a] * uCw(p, a, av, bv);
       lu12_solve(J, x);
+      if (args.dgdF) {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) args.dgdF[(int64_t)(9 * a + 3 * kk + ll) * nv + v] = (float)x[a];
+      }
       double Z[9];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -493,19 +518,25 @@ __global__ void k_rotate_tangent(int64_t nv, const int32_t* gid, const double* g
   }
 }
 
-void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st) {
+void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st, LaunchTimer* timer) {
   const int bs = 64;
   const int64_t nb = (a.nvox + bs - 1) / bs;
   const int nb_slow = (int)std::min<int64_t>(nb, 4096);
   hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, st, a.stats);
-  if (fp32) {
-    hipLaunchKernelGGL(k_slip_fast<true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
-    hipLaunchKernelGGL(k_slip_slow<true>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
-    hipLaunchKernelGGL((k_stress_tangent<float, true>), dim3((unsigned)nb), dim3(bs), 0, st, a);
-  } else {
-    hipLaunchKernelGGL(k_slip_fast<false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
-    hipLaunchKernelGGL(k_slip_slow<false>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
-    hipLaunchKernelGGL((k_stress_tangent<double, false>), dim3((unsigned)nb), dim3(bs), 0, st, a);
+  {
+    TimedLaunch t(timer, KF_SLIP_FAST, a.nvox, st);
+    if (fp32) launch(k_slip_fast<true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    else launch(k_slip_fast<false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+  }
+  {
+    TimedLaunch t(timer, KF_SLIP_SLOW, a.nvox, st);
+    if (fp32) launch(k_slip_slow<true>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
+    else launch(k_slip_slow<false>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
+  }
+  {
+    TimedLaunch t(timer, KF_STRESS_TANGENT, a.nvox, st);
+    if (fp32) launch(k_stress_tangent<float, true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    else launch(k_stress_tangent<double, false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
   }
 }
 

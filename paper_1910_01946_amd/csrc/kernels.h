@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "timing.h"
+
 namespace rve {
 
 // Material constants of one RVE, device resident (read through the scalar cache).
@@ -37,6 +39,11 @@ struct ConstArgs {
   int32_t* stats;                // device {max local iterations, failures, work-list length, -}
   int32_t* work;                 // device work list, nvox entries
   int32_t* iters;                // per voxel local iterations (negative: failed), may be null
+  float* dgdF;                   // d(dg)/dF_c at the converged state, 12 x 9 per voxel (crystal
+                                 // frame, index (9a + 3k + l) * nvox + v); written with K, may be null
+  double lam_base;               // dg (and dgdF) were computed at F + lam_base * dF
+  int32_t predict;               // 1: the first pass starts from dg + (lam - lam_base) dgdF : dF_c
+  int32_t pad;
 };
 
 struct CommitArgs {
@@ -50,7 +57,7 @@ struct CommitArgs {
   const double* rho_gnd;
 };
 
-void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st);
+void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st, LaunchTimer* timer = nullptr);
 void launch_commit(const CommitArgs& a, hipStream_t st);
 void launch_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc, double* Ks,
                            hipStream_t st);

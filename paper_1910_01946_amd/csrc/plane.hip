@@ -16,7 +16,6 @@
 #include "spectral.h"
 
 #include <algorithm>
-#include <mutex>
 
 namespace rve {
 
@@ -290,25 +289,43 @@ static int plane_ppt(const GridPlan& g) {
 
 bool plane_fits(const GridPlan& g, bool fp32) { return plane_lds(g, fp32) <= 150 * 1024 && plane_ppt(g) <= 33; }
 
+// bytes: LDS per work-group of the device; the kernel's static LDS is taken off it.
 template <typename K>
-static void allow_lds_plane(K kernel, size_t bytes) {
-  static std::mutex mu;
-  static size_t granted = 65536;
-  if (bytes > 65536) {
-    std::lock_guard<std::mutex> lock(mu);
-    if (bytes > granted) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bytes);
-      granted = bytes;
-    }
-  }
+static hipError_t lds_limit(K kernel, int bytes) {
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes - (int)fa.sharedSizeBytes);
+}
+
+template <typename T, int PPT>
+static hipError_t plane_limits_ppt(int bytes) {
+  hipError_t e = hipSuccess, f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_T, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_F64, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_FPI, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_CG, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_RESID, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_OUT64, PPT>, bytes)) != hipSuccess) e = f;
+  return e;
+}
+
+hipError_t set_plane_lds_limits(int bytes) {
+  hipError_t e = hipSuccess, f;
+  if ((f = plane_limits_ppt<float, 9>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<float, 17>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<float, 33>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<double, 9>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<double, 17>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<double, 33>(bytes)) != hipSuccess) e = f;
+  return e;
 }
 
 template <typename T, int SRC, int PPT>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  allow_lds_plane(k_plane_fwd<T, SRC, PPT>, sh);
-  hipLaunchKernelGGL((k_plane_fwd<T, SRC, PPT>), dim3(9, g.nz), dim3(256), sh, st, g, a, cg);
+  launch(k_plane_fwd<T, SRC, PPT>, dim3(9, g.nz), dim3(256), (uint32_t)sh, st, g, a, cg);
 }
 
 template <typename T, int SRC>
@@ -334,8 +351,7 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CG
 template <typename T, int MODE, int PPT>
 static void inv_launch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  allow_lds_plane(k_plane_inv<T, MODE, PPT>, sh);
-  hipLaunchKernelGGL((k_plane_inv<T, MODE, PPT>), dim3(9, g.nz), dim3(256), sh, st, g, a);
+  launch(k_plane_inv<T, MODE, PPT>, dim3(9, g.nz), dim3(256), (uint32_t)sh, st, g, a);
 }
 
 template <typename T, int MODE>
@@ -367,8 +383,8 @@ int prep_blocks(const GridPlan& g) {
 
 void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st) {
   const int nb = prep_blocks(g);
-  if (fp32) hipLaunchKernelGGL(k_cg_prep<float>, dim3(nb), dim3(256), 0, st, g.nvox, a);
-  else hipLaunchKernelGGL(k_cg_prep<double>, dim3(nb), dim3(256), 0, st, g.nvox, a);
+  if (fp32) launch(k_cg_prep<float>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else launch(k_cg_prep<double>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
 }
 
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <stdexcept>
 #include <string>
@@ -312,6 +313,17 @@ static bool trace_on() {
   return on == 1;
 }
 
+// RVE_PREDICT=0 in the environment starts every local solve from the previous slip
+// increments instead of their first-order prediction (same converged result).
+static bool prediction_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = std::getenv("RVE_PREDICT");
+    on = (e && e[0] == '0') ? 0 : 1;
+  }
+  return on == 1;
+}
+
 // ------------------------------------------------------------------------------------
 // one RVE on the device
 // ------------------------------------------------------------------------------------
@@ -331,6 +343,101 @@ static bool plane_enabled() {
   return !(e && e[0] == '0');
 }
 
+// Times the launches of the families in mask with HIP events that the kernel dispatch
+// itself records at the kernel's start and end (on the launching stream), and accumulates
+// launch count, duration and algorithmic bytes per family.
+// Launches inside a conjugate-gradient solve carry the iteration they belong to (tag), so
+// that the launches issued past the end of the solve (they return at once) are dropped.
+struct EventTimer final : LaunchTimer {
+  uint32_t mask = 0;
+  int tag = -1;  // CG iteration of the launches being issued; -1 outside CG
+  struct Rec {
+    int family, tag;
+    hipEvent_t a, b;
+    int64_t bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[KF_COUNT] = {}, close_[KF_COUNT] = {};
+  int64_t launches[KF_COUNT] = {};
+  double ms[KF_COUNT] = {}, bytes[KF_COUNT] = {};
+
+  bool on(int f) const { return (mask >> f) & 1u; }
+  hipEvent_t take() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  // The launch between begin() and end() records the two events at its own start and end.
+  void begin(int f, hipStream_t) override {
+    if (!on(f)) return;
+    LaunchEvents& ev = pending_launch_events();
+    ev.start = take();
+    ev.stop = take();
+    open[f] = ev.start;
+    close_[f] = ev.stop;
+  }
+  void end(int f, int64_t b, hipStream_t) override {
+    if (!on(f)) return;
+    pending_launch_events() = LaunchEvents{};
+    pending.push_back({f, tag, open[f], close_[f], b});
+  }
+  // Accumulate the recorded launches (their stream has been synchronised).  live_iters:
+  // iterations the CG solve completed; its transform launches of later iterations, and its
+  // vector-update launches after the one that found convergence, did no work.
+  void resolve(int live_iters = 1 << 30) {
+    for (const Rec& r : pending) {
+      const bool live = r.tag < 0 || (r.family == KF_CG_PREP ? r.tag <= live_iters : r.tag < live_iters);
+      if (live) {
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, r.a, r.b));
+        launches[r.family] += 1;
+        ms[r.family] += t;
+        bytes[r.family] += (double)r.bytes;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset(uint32_t m) {
+    mask = m;
+    for (int f = 0; f < KF_COUNT; ++f) launches[f] = 0, ms[f] = 0.0, bytes[f] = 0.0;
+  }
+  ~EventTimer() override {
+    for (const Rec& r : pending) (void)hipEventDestroy(r.a), (void)hipEventDestroy(r.b);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Algorithmic bytes of one launch (compulsory HBM traffic: every input read once, every
+// output written once).  T = spectral precision, nv voxels, ns = nxh ny nz spectral points.
+static int64_t bytes_mid(const GridPlan& g, bool fp32) { return 2 * 9 * 2 * (fp32 ? 4 : 8) * g.nspec; }
+static int64_t bytes_cg_prep(const GridPlan& g, bool fp32, bool first) {
+  // x, p, r, q, K read and x, r, y written (first iteration: r, K read and y written)
+  return (first ? 99 : 144) * (fp32 ? 4 : 8) * g.nvox + 4 * g.nvox;
+}
+static int64_t bytes_plane_fwd_cg(const GridPlan& g, bool fp32) {
+  const int t = fp32 ? 4 : 8;
+  return 9 * t * g.nvox + 9 * 2 * t * g.nspec;  // y read, spectrum written
+}
+static int64_t bytes_plane_inv_cg(const GridPlan& g, bool fp32) {
+  const int t = fp32 ? 4 : 8;
+  return 9 * 2 * t * g.nspec + 45 * t * g.nvox;  // spectrum, r read; p, q read and written
+}
+static int64_t bytes_plane_fwd_f64(const GridPlan& g, bool fp32) {
+  return 9 * 8 * g.nvox + 9 * 2 * (fp32 ? 4 : 8) * g.nspec;  // FP64 field read, spectrum written
+}
+static int64_t bytes_plane_inv_resid(const GridPlan& g, bool fp32) {
+  const int t = fp32 ? 4 : 8;
+  return 9 * 2 * t * g.nspec + 27 * t * g.nvox;  // spectrum read; x, r, p written
+}
+
 struct RVE {
   Work w[2];     // [0] FP64, [1] FP32 (allocated on first use)
   int n[3];
@@ -344,9 +451,12 @@ struct RVE {
   DevBuf F, F_prev, Fp, rho_ssd, rho_gnd, nye, dg, P;
   // work
   DevBuf F_work, F_try, P_work, dg_saved, cg, partial, blk;
+  DevBuf dgdF;  // FP32 slip sensitivity d(dg)/dF_c, 108 x nvox, written with the tangent
   int64_t fp64_fallbacks = 0;
   hipStream_t stream = nullptr;   // each RVE runs on its own stream
   CGState* host_cg = nullptr;     // pinned copy of the CG scalars
+  EventTimer timer;               // optional launch timing
+  LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
     if (host_cg) (void)hipHostFree(host_cg);
     if (stream) (void)hipStreamDestroy(stream);
@@ -436,6 +546,7 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   R.F_try.alloc(f9);
   R.P_work.alloc(f9);
   R.dg_saved.alloc(f12);
+  R.dgdF.alloc(sizeof(float) * 108 * (size_t)nv);
   HIPCHECK(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));
   HIPCHECK(hipHostMalloc((void**)&R.host_cg, sizeof(CGState), hipHostMallocDefault));
   Work& w = work(R, C.fp32);
@@ -456,10 +567,13 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
 struct LocalStats {
   int max_iters = 0;
   int failures = 0;
+  int slow = 0;  // voxels handed to the continuation kernel
 };
 
+// predict: start the local solve from dg + (lam - lam_base) d(dg)/dF : dF, where dg and
+// d(dg)/dF hold the converged solution of the previous call at F + lam_base dF.
 static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, const void* dF, double lam, double* F_out,
-                                   double dt, bool tangent) {
+                                   double dt, bool tangent, bool predict = false, double lam_base = 0.0) {
   ConstArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nvox = R.nvox;
@@ -479,14 +593,21 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.dt = dt;
   a.stats = R.blk.as<int32_t>();
   a.work = R.blk.as<int32_t>() + 4;
-  launch_constitutive(a, w.fp32, R.stream);
+  a.dgdF = tangent ? R.dgdF.as<float>() : nullptr;
+  a.predict = (predict && dF && prediction_enabled()) ? 1 : 0;
+  a.lam_base = lam_base;
+  launch_constitutive(a, w.fp32, R.stream, R.tm());
   check_launch("constitutive");
   int32_t st4[4];
   HIPCHECK(hipMemcpyAsync(st4, R.blk.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, R.stream));
   HIPCHECK(hipStreamSynchronize(R.stream));
+  R.timer.resolve();
   LocalStats ls;
   ls.max_iters = st4[0];
   ls.failures = st4[1];
+  ls.slow = st4[2];
+  if (trace_on()) std::fprintf(stderr, "[rve] local solve: %d of %lld voxels on the continuation path, max it %d\n",
+                               ls.slow, (long long)R.nvox, ls.max_iters);
   return ls;
 }
 
@@ -496,7 +617,10 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
   const GridPlan& g = w.plan.g;
   if (w.plane) {
     PlaneArgs pa{PF_F64, P64, w.spec.p};
-    launch_plane_fwd(g, w.fp32, pa, nullptr, R.stream);
+    {
+      TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_f64(g, w.fp32), R.stream);
+      launch_plane_fwd(g, w.fp32, pa, nullptr, R.stream);
+    }
     MidArgs m;
     std::memset(&m, 0, sizeof(m));
     m.op = MID_GREEN;
@@ -506,7 +630,10 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
       m.dc_target[c] = target ? target[c] : 0.0;
     }
     m.inv_n = 1.0 / (double)g.nvox;
-    launch_mid(g, w.fp32, m, R.stream);
+    {
+      TimedLaunch t(R.tm(), KF_MID, bytes_mid(g, w.fp32), R.stream);
+      launch_mid(g, w.fp32, m, R.stream);
+    }
     PlaneInvArgs pi;
     std::memset(&pi, 0, sizeof(pi));
     pi.mode = PI_RESID;
@@ -515,11 +642,15 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
     pi.r = w.r.p;
     pi.p = w.p.p;
     pi.partial = R.partial.as<double>();
-    launch_plane_inv(g, w.fp32, pi, R.stream);
+    {
+      TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_resid(g, w.fp32), R.stream);
+      launch_plane_inv(g, w.fp32, pi, R.stream);
+    }
     launch_cg_start(R.cg.as<CGState>(), R.partial.as<double>(), plane_blocks(g), 0.0, 0, R.stream);
     check_launch("residual");
     HIPCHECK(hipMemcpyAsync(R.host_cg, R.cg.p, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
     HIPCHECK(hipStreamSynchronize(R.stream));
+    R.timer.resolve();
     return R.host_cg->rr;
   }
   XFwdArgs xf;
@@ -624,16 +755,31 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pi.cg = cg;
   pi.partial = part + 2048;
   const int chunk = 4;
+  int issued = 0;  // CG iterations launched so far
   for (;;) {
     if (R.host_cg->done) break;
-    for (int i = 0; i < chunk && w.plane; ++i) {
-      launch_cg_prep(g, w.fp32, pr, R.stream);
+    for (int i = 0; i < chunk && w.plane; ++i, ++issued) {
+      R.timer.tag = issued;
+      {
+        TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, issued == 0), R.stream);
+        launch_cg_prep(g, w.fp32, pr, R.stream);
+      }
       launch_cg_beta(cg, part, prep_blocks(g), R.stream);
-      launch_plane_fwd(g, w.fp32, pa, cg, R.stream);
-      launch_mid(g, w.fp32, m, R.stream);
-      launch_plane_inv(g, w.fp32, pi, R.stream);
+      {
+        TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_cg(g, w.fp32), R.stream);
+        launch_plane_fwd(g, w.fp32, pa, cg, R.stream);
+      }
+      {
+        TimedLaunch t(R.tm(), KF_MID, bytes_mid(g, w.fp32), R.stream);
+        launch_mid(g, w.fp32, m, R.stream);
+      }
+      {
+        TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_cg(g, w.fp32), R.stream);
+        launch_plane_inv(g, w.fp32, pi, R.stream);
+      }
       launch_cg_alpha(cg, part + 2048, plane_blocks(g), R.stream);
     }
+    R.timer.tag = -1;
     for (int i = 0; i < chunk && !w.plane; ++i) {
       launch_xfwd(g, w.fp32, xf, R.stream);
       launch_cg_beta(cg, part, nb, R.stream);
@@ -647,6 +793,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
     HIPCHECK(hipMemcpyAsync(R.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
     HIPCHECK(hipStreamSynchronize(R.stream));
   }
+  R.timer.resolve(R.host_cg->iter);
   done_code = R.host_cg->done;
   return R.host_cg->iter;
 }
@@ -764,10 +911,12 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
       return RVE_ENOCONV;
     }
     st.newton_iters++;
-    double lam = 1.0, res_try = 0.0;
+    double lam = 1.0, res_try = 0.0, lam_base = 0.0;
     bool accepted = false;
     for (int ls_i = 0; ls_i <= C.opt.max_backtrack; ++ls_i) {
-      LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true);
+      LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true, true,
+                                       lam_base);
+      lam_base = lam;
       st.local_iters_max = std::max(st.local_iters_max, l2.max_iters);
       if (l2.failures == 0) {
         const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
@@ -922,6 +1071,26 @@ static int32_t guarded(Fn fn) {
   }
 }
 
+// Raise the dynamic-LDS limit of the LDS-staged kernels to what the current device
+// allows, once per device, before any launch on it: changing a kernel attribute while
+// other threads launch that kernel is not safe.  Best effort: a launch that asks for more
+// LDS than the device grants fails and is reported by the launch check that follows it.
+static void prepare_device() {
+  static std::mutex mu;
+  static std::vector<int> done;
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+  int lds = 0;
+  HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const hipError_t e1 = set_spectral_lds_limits(lds), e2 = set_plane_lds_limits(lds);
+  if ((e1 != hipSuccess || e2 != hipSuccess) && trace_on())
+    std::fprintf(stderr, "[rve] dynamic LDS limit not raised: %s\n", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  (void)hipGetLastError();
+  done.push_back(dev);
+}
+
 extern "C" {
 
 int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt, rve_handle* out) {
@@ -944,6 +1113,7 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
     C->fp32 = o.precision == RVE_MIXED;
     C->device = o.device;
     HIPCHECK(hipSetDevice(C->device));
+    prepare_device();
     C->stream = (hipStream_t)o.stream;
     if (const char* e = std::getenv("RVE_WORKERS")) C->workers = std::max(1, std::atoi(e));
     for (int i = 0; i < n_rve; ++i) {
@@ -951,6 +1121,38 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
       init_rve(*C, *C->rves.back(), descs[i]);
     }
     *out = C.release();
+    return RVE_OK;
+  });
+}
+
+int32_t rve_timing_start(rve_handle h, uint32_t mask) {
+  return guarded([&]() -> int32_t {
+    if (!h) throw Error(RVE_EINVAL, "null handle");
+    if (mask >> KF_COUNT) throw Error(RVE_EINVAL, "unknown kernel family in mask");
+    HIPCHECK(hipSetDevice(h->device));
+    for (auto& R : h->rves) {
+      HIPCHECK(hipStreamSynchronize(R->stream));
+      R->timer.resolve();
+      R->timer.reset(mask);
+    }
+    return RVE_OK;
+  });
+}
+
+int32_t rve_timing_read(rve_handle h, int32_t family, int64_t* launches, double* total_ms, double* units) {
+  return guarded([&]() -> int32_t {
+    if (!h) throw Error(RVE_EINVAL, "null handle");
+    if (family < 0 || family >= KF_COUNT) throw Error(RVE_EINVAL, "unknown kernel family");
+    int64_t n = 0;
+    double t = 0.0, u = 0.0;
+    for (auto& R : h->rves) {
+      n += R->timer.launches[family];
+      t += R->timer.ms[family];
+      u += R->timer.bytes[family];
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = t;
+    if (units) *units = u;
     return RVE_OK;
   });
 }
@@ -1203,6 +1405,7 @@ int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, cons
                     const double* dc_target, double* out, void* stream) {
   return guarded([&]() -> int32_t {
     if (!n || !A || !mask || !out) throw Error(RVE_EINVAL, "null argument");
+    prepare_device();
     const bool fp32 = precision == RVE_MIXED;
     hipStream_t st = (hipStream_t)stream;
     Plan P;
@@ -1261,6 +1464,7 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
   return guarded([&]() -> int32_t {
     if (!n || !Fp || !nye) throw Error(RVE_EINVAL, "null argument");
     if (!(std::isfinite(h) && h > 0)) throw Error(RVE_EINVAL, "h must be > 0");
+    prepare_device();
     const bool fp32 = precision == RVE_MIXED;
     hipStream_t st = (hipStream_t)stream;
     Plan P;

@@ -144,6 +144,10 @@ struct PrepArgs {
 };
 
 bool plane_fits(const GridPlan& g, bool fp32);
+// Raise the dynamic-LDS limit of every LDS-staged spectral kernel to bytes.  Called once
+// per device before the first launch (never concurrently with launches).
+hipError_t set_spectral_lds_limits(int bytes);
+hipError_t set_plane_lds_limits(int bytes);
 int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CGState* cg, hipStream_t st);

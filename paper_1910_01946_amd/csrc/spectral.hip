@@ -17,7 +17,6 @@
 // update and residual norm, Nye tensor and GND densities, or plain output).
 #include "spectral.h"
 
-#include <mutex>
 
 namespace rve {
 
@@ -500,20 +499,35 @@ __global__ void k_predictor(const double* F, const double* F_prev, Corr9 corr, d
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
-// Raise a kernel's dynamic-LDS limit once when a launch needs more than 64 KiB (gfx950
-// has 160 KiB of LDS per compute unit).
+// bytes: LDS per work-group of the device; the kernel's static LDS is taken off it.
 template <typename K>
-static void allow_lds(K kernel, size_t bytes) {
-  static std::mutex mu;
-  static size_t granted = 65536;
-  if (bytes > 65536) {
-    std::lock_guard<std::mutex> lock(mu);
-    if (bytes > granted) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bytes);
-      granted = bytes;
-    }
-  }
+static hipError_t lds_limit(K kernel, int bytes) {
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes - (int)fa.sharedSizeBytes);
+}
+
+template <typename T>
+static hipError_t spectral_limits(int bytes) {
+  hipError_t e = hipSuccess, f;
+  if ((f = lds_limit(k_xfwd<T, XF_FIELD64>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xfwd<T, XF_CG>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xfwd<T, XF_FP_MINUS_I>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_yfft<T>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_mid<T, MID_GREEN>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_mid<T, MID_CURL>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xinv<T, XI_RESID>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xinv<T, XI_CG>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xinv<T, XI_NYE>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_xinv<T, XI_OUT64>, bytes)) != hipSuccess) e = f;
+  return e;
+}
+
+hipError_t set_spectral_lds_limits(int bytes) {
+  hipError_t e = spectral_limits<float>(bytes), f = spectral_limits<double>(bytes);
+  return e != hipSuccess ? e : f;
 }
 
 static int xthreads(const GridPlan& g) {
@@ -546,10 +560,8 @@ void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGSta
   const dim3 grid((g.nxh + g.ty - 1) / g.ty, g.nz, 9);
   const size_t sh = (size_t)g.ny * (g.ty + 1) * (fp32 ? 8 : 16);
   if (fp32) {
-    allow_lds(k_yfft<float>, sh);
     hipLaunchKernelGGL(k_yfft<float>, grid, dim3(256), sh, st, g, spec, sign, cg);
   } else {
-    allow_lds(k_yfft<double>, sh);
     hipLaunchKernelGGL(k_yfft<double>, grid, dim3(256), sh, st, g, spec, sign, cg);
   }
 }
@@ -559,19 +571,15 @@ void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) 
   const size_t sh = ((size_t)9 * g.nz * (g.tz + 1) + g.nz) * (fp32 ? 8 : 16);
   if (fp32) {
     if (a.op == MID_GREEN) {
-      allow_lds(k_mid<float, MID_GREEN>, sh);
-      hipLaunchKernelGGL((k_mid<float, MID_GREEN>), grid, dim3(256), sh, st, g, a);
+      launch(k_mid<float, MID_GREEN>, grid, dim3(256), (uint32_t)sh, st, g, a);
     } else {
-      allow_lds(k_mid<float, MID_CURL>, sh);
-      hipLaunchKernelGGL((k_mid<float, MID_CURL>), grid, dim3(256), sh, st, g, a);
+      launch(k_mid<float, MID_CURL>, grid, dim3(256), (uint32_t)sh, st, g, a);
     }
   } else {
     if (a.op == MID_GREEN) {
-      allow_lds(k_mid<double, MID_GREEN>, sh);
-      hipLaunchKernelGGL((k_mid<double, MID_GREEN>), grid, dim3(256), sh, st, g, a);
+      launch(k_mid<double, MID_GREEN>, grid, dim3(256), (uint32_t)sh, st, g, a);
     } else {
-      allow_lds(k_mid<double, MID_CURL>, sh);
-      hipLaunchKernelGGL((k_mid<double, MID_CURL>), grid, dim3(256), sh, st, g, a);
+      launch(k_mid<double, MID_CURL>, grid, dim3(256), (uint32_t)sh, st, g, a);
     }
   }
 }
