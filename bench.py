@@ -10,13 +10,14 @@ GPU before the timed region; rve_create is outside it.
 The default workload is the 64^3 strain-gradient RVE (64 Voronoi grains, Cu, 5 % tension
 in 50 increments) in the mixed-precision form; the same increments are then timed in the
 plain FP64 form, and the macroscopic stress of the two is compared.  The roofline object
-reports the z-FFT / Green-operator kernel (the largest share of the timed region), timed
-with HIP events on the RVE's stream in a replay of the timed increments from the same
-saved state; the headline value comes from the uninstrumented pass.
+reports the kernel family with the largest share of the timed increments, timed with
+events that the kernel dispatches record on the RVE's stream, in replays of the timed
+increments from the same saved state; the headline value comes from the uninstrumented
+pass.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cu64|cu16|al128|sweep32|cu64g100]
                        [--precision mixed|fp64] [--no-fp64-compare] [--no-cpu-baseline]
-                       [--no-roofline] [--roofline-kernel mid|cg_prep|plane_fwd|...]
+                       [--no-roofline] [--roofline-kernel auto|mid|cg_prep|plane_fwd|...]
        python bench.py --copy-calibration   (plain device copy of known size, for the
                                              FETCH_SIZE / WRITE_SIZE counter scale)
 """
@@ -56,23 +57,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="cu64")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--newton-tol", type=float, default=1e-6)
     ap.add_argument("--cg-tol", type=float, default=1e-3)
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--roofline-kernel", default="mid", choices=list(FAMILY_KERNELS),
-                    help="kernel family timed for the roofline object (default: the z-FFT/Green kernel, "
-                         "the largest share of the timed region)")
+    ap.add_argument("--roofline-kernel", default="auto", choices=["auto"] + list(FAMILY_KERNELS),
+                    help="kernel family of the roofline object (auto: the largest share of the timed "
+                         "increments)")
     ap.add_argument("--rves", type=int, default=None, help="use only the first R RVEs of the workload")
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
 
 # (warmup, timed) increments per workload
-DEFAULTS = {"c1": (2, 10), "c2": (3, 8), "c3": (2, 3), "c4": (2, 3), "c5": (3, 8)}
+DEFAULTS = {"cu16": (2, 10), "cu64": (3, 8), "al128": (2, 3), "sweep32": (2, 3), "cu64g100": (3, 8)}
 
 
 def cpu_baseline(workload: str):
@@ -142,9 +143,9 @@ def _timed(h, path, W, K, tag):
 def run_leg(lib, rves, path, prec, W, K, args, roof_family=None):
     """Warm up W increments, then time K increments without instrumentation.  With
     roof_family, the committed state after the warmup is restored and the same K
-    increments are replayed twice: once with HIP events around the launches of that
-    family only (its live average launch duration), once with events around every family
-    (the share of each in that replay)."""
+    increments are replayed: once with kernel-timing events on every family (the share
+    of each; "auto" then picks the largest), once with events on the chosen family only
+    (its live average launch duration)."""
     h = lib.Homogenizer(rves, precision=prec, newton_tol=args.newton_tol, cg_tol=args.cg_tol, max_cg=3000,
                         max_newton=150)
     tag = "mixed" if prec == lib.RVE_MIXED else "fp64"
@@ -157,13 +158,15 @@ def run_leg(lib, rves, path, prec, W, K, args, roof_family=None):
     out = {"value": vi / T, "T": T, "vi": vi, "iters": it_stats, "P": P}
     if roof_family:
         h.load_state(saved)
-        h.timing_start([roof_family])
-        _, T1, it1 = _timed(h, path, W, K, tag + " replay, events on " + roof_family)
-        out["roof"] = (roof_family, h.timing_read(roof_family), T1, it1 == it_stats)
-        h.load_state(saved)
         h.timing_start(list(FAMILY_KERNELS))
         _, T2, _ = _timed(h, path, W, K, tag + " replay, events on all families")
         out["share"] = {f: h.timing_read(f)[1] / (1e3 * T2) for f in FAMILY_KERNELS}
+        if roof_family == "auto":
+            roof_family = max(out["share"], key=out["share"].get)
+        h.load_state(saved)
+        h.timing_start([roof_family])
+        _, T1, it1 = _timed(h, path, W, K, tag + " replay, events on " + roof_family)
+        out["roof"] = (roof_family, h.timing_read(roof_family), T1, it1 == it_stats)
         h.timing_start(())
     h.close()
     return out

@@ -34,8 +34,12 @@ __device__ __forceinline__ double block_sum2(double v, double* sh) {
   return s;
 }
 
+// Threads per plane block: the plane transforms are a chain of dependent LDS stages, so
+// more threads per plane (fewer points each) shorten the chain.
+constexpr int kPlaneThreads = 512;
+
 template <typename T, int SRC, int PPT>
-__global__ void __launch_bounds__(256) k_plane_fwd(GridPlan g, PlaneArgs a, const CGState* cg) {
+__global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, const CGState* cg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (cg && cg->done) return;
   const int c = blockIdx.x, z = blockIdx.y;
@@ -97,7 +101,7 @@ __global__ void __launch_bounds__(256) k_plane_fwd(GridPlan g, PlaneArgs a, cons
 }
 
 template <typename T, int MODE, int PPT>
-__global__ void __launch_bounds__(256) k_plane_inv(GridPlan g, PlaneInvArgs a) {
+__global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneInvArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[8];
   if (MODE == PI_CG && a.cg->done) return;
@@ -284,7 +288,7 @@ static size_t plane_lds(const GridPlan& g, bool fp32) {
 
 static int plane_ppt(const GridPlan& g) {
   const int npts = std::max(((g.ny + 1) / 2) * g.nx, g.nxh * g.ny);
-  return (npts + 255) / 256;
+  return (npts + kPlaneThreads - 1) / kPlaneThreads;
 }
 
 bool plane_fits(const GridPlan& g, bool fp32) { return plane_lds(g, fp32) <= 150 * 1024 && plane_ppt(g) <= 33; }
@@ -313,9 +317,11 @@ static hipError_t plane_limits_ppt(int bytes) {
 
 hipError_t set_plane_lds_limits(int bytes) {
   hipError_t e = hipSuccess, f;
+  if ((f = plane_limits_ppt<float, 5>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<float, 9>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<float, 17>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<float, 33>(bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_ppt<double, 5>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<double, 9>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<double, 17>(bytes)) != hipSuccess) e = f;
   if ((f = plane_limits_ppt<double, 33>(bytes)) != hipSuccess) e = f;
@@ -325,13 +331,14 @@ hipError_t set_plane_lds_limits(int bytes) {
 template <typename T, int SRC, int PPT>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_fwd<T, SRC, PPT>, dim3(9, g.nz), dim3(256), (uint32_t)sh, st, g, a, cg);
+  launch(k_plane_fwd<T, SRC, PPT>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a, cg);
 }
 
 template <typename T, int SRC>
 static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
   const int ppt = plane_ppt(g);
-  if (ppt <= 9) fwd_launch<T, SRC, 9>(g, a, cg, st);
+  if (ppt <= 5) fwd_launch<T, SRC, 5>(g, a, cg, st);
+  else if (ppt <= 9) fwd_launch<T, SRC, 9>(g, a, cg, st);
   else if (ppt <= 17) fwd_launch<T, SRC, 17>(g, a, cg, st);
   else fwd_launch<T, SRC, 33>(g, a, cg, st);
 }
@@ -351,13 +358,14 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CG
 template <typename T, int MODE, int PPT>
 static void inv_launch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_inv<T, MODE, PPT>, dim3(9, g.nz), dim3(256), (uint32_t)sh, st, g, a);
+  launch(k_plane_inv<T, MODE, PPT>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a);
 }
 
 template <typename T, int MODE>
 static void inv_dispatch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const int ppt = plane_ppt(g);
-  if (ppt <= 9) inv_launch<T, MODE, 9>(g, a, st);
+  if (ppt <= 5) inv_launch<T, MODE, 5>(g, a, st);
+  else if (ppt <= 9) inv_launch<T, MODE, 9>(g, a, st);
   else if (ppt <= 17) inv_launch<T, MODE, 17>(g, a, st);
   else inv_launch<T, MODE, 33>(g, a, st);
 }

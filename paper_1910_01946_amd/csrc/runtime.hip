@@ -264,7 +264,11 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
   g.ly = std::min(ly, ny_even);
   g.ty = std::min(16, g.nxh);
   if (g.ny * g.ty > 16 * 256) g.ty = (16 * 256) / g.ny;
-  g.tz = std::max(1, std::min(g.nxh, (18 * 256) / (9 * g.nz)));
+  // kx columns per z-pass block: nz * tz about 256 (9 points per thread; more than 2 blocks
+  // per compute unit at 64^3), never more than 18 points per thread
+  g.tz = std::max(1, std::min(g.nxh, 256 / g.nz));
+  g.tz = std::max(1, std::min(g.tz, (18 * 256) / (9 * g.nz)));
+  if (const char* e = std::getenv("RVE_TZ")) g.tz = std::max(1, std::min(g.tz, std::atoi(e)));
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
     const int m = n[d];

@@ -93,6 +93,31 @@ struct XInvArgs {
 
 void launch_xfwd(const GridPlan& g, bool fp32, const XFwdArgs& a, hipStream_t st);
 void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGState* cg, hipStream_t st);
+// ---- CG scalar updates (device side) ----------------------------------------------
+// beta step, after r.r of the updated residual: beta = r.r / previous r.r; stop when
+// r.r <= tol2 r0.r0 (1), when it grows past 1e4 r0.r0 or is not finite (3), or at the
+// iteration cap (4).
+__device__ inline void cg_beta_update(CGState* cg, double rr) {
+  cg->beta = (cg->iter == 0) ? 0.0 : rr / cg->rr;
+  cg->rr = rr;
+  if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
+  else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;
+  else if (cg->iter >= cg->max_iter) cg->done = 4;
+}
+
+// alpha step, after p.q: alpha = r.r / p.q; a non-positive (or non-finite) p.q is a
+// breakdown (2).
+__device__ inline void cg_alpha_update(CGState* cg, double pq) {
+  cg->pq = pq;
+  cg->iter += 1;
+  if (pq > 0.0 && pq < 1e300) {
+    cg->alpha = cg->rr / pq;
+  } else {
+    cg->alpha = 0.0;
+    cg->done = 2;
+  }
+}
+
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st);
 void launch_xinv(const GridPlan& g, bool fp32, const XInvArgs& a, hipStream_t st);
 int xfwd_blocks(const GridPlan& g);

@@ -172,7 +172,15 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   if (a.cg && a.cg->done) return;
   const int ny = g.ny, nz = g.nz, nxh = g.nxh, tz = g.tz, tzp = g.tz + 1;
-  const int ky = blockIdx.y, kx0 = blockIdx.x * tz;
+  // XCD-aware order: consecutive hardware block ids are dealt to the 8 XCDs in turn; each
+  // XCD takes a contiguous range of (ky, kx tile) so that the cache lines shared by
+  // neighbouring tiles and rows are fetched and written back through a single L2.
+  const int ntile = (nxh + tz - 1) / tz;
+  const int nblk = ntile * ny;
+  const int per = (nblk + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (logical >= nblk) return;
+  const int ky = logical / ntile, kx0 = (logical % ntile) * tz;
   const int tid = threadIdx.x, nthr = blockDim.x;
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   cplx<T>* twz = buf + 9 * nz * tzp;
@@ -429,32 +437,13 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
 __global__ void k_cg_beta(CGState* cg, const double* partial, int n) {
   if (cg->done) return;
   const double rr = reduce_partials(partial, n);
-  if (threadIdx.x == 0) {
-    if (cg->iter == 0) {
-      cg->beta = 0.0;
-    } else {
-      cg->beta = rr / cg->rr;
-    }
-    cg->rr = rr;
-    if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
-    else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;  // diverging (or not finite)
-    else if (cg->iter >= cg->max_iter) cg->done = 4;
-  }
+  if (threadIdx.x == 0) cg_beta_update(cg, rr);
 }
 
 __global__ void k_cg_alpha(CGState* cg, const double* partial, int n) {
   if (cg->done) return;
   const double pq = reduce_partials(partial, n);
-  if (threadIdx.x == 0) {
-    cg->pq = pq;
-    cg->iter += 1;
-    if (pq > 0.0 && pq < 1e300) {
-      cg->alpha = cg->rr / pq;
-    } else {
-      cg->alpha = 0.0;
-      cg->done = 2;  // breakdown: the operator is not positive along p
-    }
-  }
+  if (threadIdx.x == 0) cg_alpha_update(cg, pq);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -566,8 +555,13 @@ void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGSta
   }
 }
 
+int mid_blocks(const GridPlan& g) {
+  const int nblk = ((g.nxh + g.tz - 1) / g.tz) * g.ny;
+  return 8 * ((nblk + 7) / 8);
+}
+
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) {
-  const dim3 grid((g.nxh + g.tz - 1) / g.tz, g.ny);
+  const dim3 grid(mid_blocks(g));
   const size_t sh = ((size_t)9 * g.nz * (g.tz + 1) + g.nz) * (fp32 ? 8 : 16);
   if (fp32) {
     if (a.op == MID_GREEN) {

@@ -235,52 +235,52 @@ def voxel_size_for(d: float, n_grains: int, n: int) -> float:
     return d * n_grains ** (1.0 / 3.0) / n
 
 
-C4_SIZES = (32, 40, 48, 64, 72, 80, 96)
-C4_MATERIALS = ("Cu", "Ag", "Ni")
+SWEEP_SIZES = (32, 40, 48, 64, 72, 80, 96)
+SWEEP_MATERIALS = ("Cu", "Ag", "Ni")
 
 
 def workload(name: str, n_override=None, n_inc_override=None):
     """Return (list of RVEs, LoadPath, description) for a named benchmark workload.
 
-    c1: 16^3, 8 grains, Cu, tau0 = 10 MPa, no gradient term, 1% in 20 increments at 1e-3/s.
-    c2: 64^3, 64 grains, Cu, d = 50 um, rho_i = 1.2e12 (1e11 per system), 5% in 50 at 1e-4/s.
-    c3: 128^3, 200 grains, Al, d = 20 um, 5% in 50 increments at 1e-4/s.
-    c4: 32 RVEs of uneven size (32^3..96^3), 16..128 grains, d log-uniform in [10, 200] um,
-        Cu/Ag/Ni, 3% in 30 increments at 1e-4/s.
-    c5: 64^3, 100 grains, Cu, d = 30 um, 4% in 40 increments at 1e-4/s.
+    cu16:     16^3, 8 grains, Cu, tau0 = 10 MPa, no gradient term, 1% in 20 increments at 1e-3/s.
+    cu64:     64^3, 64 grains, Cu, d = 50 um, rho_i = 1.2e12 (1e11 per system), 5% in 50 at 1e-4/s.
+    al128:    128^3, 200 grains, Al, d = 20 um, 5% in 50 increments at 1e-4/s.
+    sweep32:  32 RVEs of uneven size (32^3..96^3), 16..128 grains, d log-uniform in
+              [10, 200] um, Cu/Ag/Ni, 3% in 30 increments at 1e-4/s (a grain-size sweep).
+    cu64g100: 64^3, 100 grains, Cu, d = 30 um, 4% in 40 increments at 1e-4/s.
     """
-    if name == "c1":
+    if name == "cu16":
         n = n_override or 16
         mat = material("Cu", tau0=10e6, c_gnd=0.0)
         rves = [voronoi_rve(101, n, 8, voxel_size_for(50e-6, 8, n), mat)]
         path = uniaxial_tension(0.01, n_inc_override or 20, 1e-3)
-    elif name == "c2":
+    elif name == "cu64":
         n = n_override or 64
         mat = material("Cu", rho0=1e11, c_gnd=1.0)
         rves = [voronoi_rve(102, n, 64, voxel_size_for(50e-6, 64, n), mat)]
         path = uniaxial_tension(0.05, n_inc_override or 50, 1e-4)
-    elif name == "c3":
+    elif name == "al128":
         n = n_override or 128
         mat = material("Al", rho0=1e11, c_gnd=1.0)
         rves = [voronoi_rve(103, n, 200, voxel_size_for(20e-6, 200, n), mat)]
         path = uniaxial_tension(0.05, n_inc_override or 50, 1e-4)
-    elif name == "c4":
+    elif name == "sweep32":
         rves = []
         for r in range(32):
             rng = SplitMix64(1040 + r)
-            nr = C4_SIZES[min(int(rng.uniform() * len(C4_SIZES)), len(C4_SIZES) - 1)]
+            nr = SWEEP_SIZES[min(int(rng.uniform() * len(SWEEP_SIZES)), len(SWEEP_SIZES) - 1)]
             ng = 16 + min(int(rng.uniform() * 113), 112)
             d = 10e-6 * math.exp(rng.uniform() * math.log(20.0))
             if n_override:
                 nr = n_override
-            mat = material(C4_MATERIALS[r % 3], rho0=1e11, c_gnd=1.0)
+            mat = material(SWEEP_MATERIALS[r % 3], rho0=1e11, c_gnd=1.0)
             centers = grain_centers(rng, ng, (nr, nr, nr))
             quats = shoemake_quaternions(rng, ng)
             gid = periodic_voronoi((nr, nr, nr), centers)
             rves.append(RVE(n=(nr, nr, nr), voxel_size=voxel_size_for(d, ng, nr),
                             grain_of_voxel=gid, quats=quats, material=mat, seed=1040 + r))
         path = uniaxial_tension(0.03, n_inc_override or 30, 1e-4)
-    elif name == "c5":
+    elif name == "cu64g100":
         n = n_override or 64
         mat = material("Cu", rho0=1e11, c_gnd=1.0)
         rves = [voronoi_rve(105, n, 100, voxel_size_for(30e-6, 100, n), mat)]

@@ -66,7 +66,7 @@ def test_constitutive_update_and_tangent(lib, amp, hard):
 
 
 @pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 4), (10, 12, 6), (16, 16, 16), (64, 64, 64),
-                                   (40, 48, 24)])
+                                   (40, 48, 24), (96, 80, 6), (128, 128, 4)])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("plane", ["1", "0"])
 def test_projection_matches_oracle(lib, shape, precision, plane, monkeypatch):

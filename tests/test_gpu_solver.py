@@ -37,9 +37,9 @@ def _run_both(lib, rve, path, n_inc, precision=0, newton_tol=1e-11, cg_tol=1e-10
 
 
 @pytest.mark.parametrize("plane", ["1", "0"])
-def test_c1_small_fp64_matches_oracle(lib, plane, monkeypatch):
+def test_cu16_at_8cubed_fp64_matches_oracle(lib, plane, monkeypatch):
     monkeypatch.setenv("RVE_PLANE", plane)
-    rves, path = synth.workload("c1", n_override=8, n_inc_override=20)
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
     o, h, out = _run_both(lib, rves[0], path, 3)
     for Po, Pg, Fo, Fg in out:
         scale = np.abs(Po).max()
@@ -52,8 +52,8 @@ def test_c1_small_fp64_matches_oracle(lib, plane, monkeypatch):
     assert rel_norm(from_abi(h.field("rho_ssd"), tensor=False), o.rho_ssd) < 1e-10
 
 
-def test_c2_small_sgcp_fp64_matches_oracle(lib):
-    rves, path = synth.workload("c2", n_override=8, n_inc_override=50)
+def test_cu64_sgcp_at_8cubed_fp64_matches_oracle(lib):
+    rves, path = synth.workload("cu64", n_override=8, n_inc_override=50)
     o, h, out = _run_both(lib, rves[0], path, 3)
     for Po, Pg, Fo, Fg in out:
         assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()

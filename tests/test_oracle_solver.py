@@ -72,7 +72,7 @@ def test_linear_elastic_solve_matches_dense_galerkin_assembly():
 
 @pytest.fixture(scope="module")
 def small_run():
-    rves, path = synth.workload("c2", n_override=6, n_inc_override=50)
+    rves, path = synth.workload("cu64", n_override=6, n_inc_override=50)
     rve = rves[0]
     rve.voxel_size = 5e-7
     s = solver.RVESolver(rve)
@@ -107,7 +107,7 @@ def test_gnd_recomputed_from_committed_fp(small_run):
 
 
 def test_periodic_translation_equivariance():
-    rves, path = synth.workload("c1", n_override=4)
+    rves, path = synth.workload("cu16", n_override=4)
     rve = rves[0]
     s1 = solver.RVESolver(rve)
     r1 = s1.run(path, n_inc=2)
@@ -122,7 +122,7 @@ def test_periodic_translation_equivariance():
 
 
 def test_without_gradient_term_voxel_size_does_not_matter():
-    rves, path = synth.workload("c1", n_override=4)
+    rves, path = synth.workload("cu16", n_override=4)
     rve = rves[0]
     out = []
     for h in (1e-6, 3e-5):

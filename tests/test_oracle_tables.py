@@ -1,4 +1,6 @@
 """Pins of the oracle's crystallographic tables (Section 2.1, Tables 1-2, eqs. 10-13)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -77,11 +79,29 @@ def test_edge_lines_are_112_and_screw_of_system():
     assert sorted(np.bincount(idx)) == [2] * 6
 
 
+def _golden_rows(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    return [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+
+
+TABLE2 = {r[0]: tuple(float(v) * 1e9 for v in r[1:]) for r in _golden_rows("table2_shear_modulus.txt")}
+
+
 @pytest.mark.parametrize("name", ["Cu", "Al", "Ni", "Ag"])
 def test_slip_plane_shear_modulus_reproduces_table2(name):
-    C11, C12, C44 = synth.TABLE2_ELASTIC[name]
+    """The printed Table 2 shear modulus follows from the printed C_ij (to ~1 %)."""
+    C11, C12, C44, mu_printed = TABLE2[name]
     mu = elasticity.slip_plane_shear_modulus(C11, C12, C44)
-    assert abs(mu / synth.TABLE2_MU[name] - 1) < 0.012
+    assert abs(mu / mu_printed - 1) < 0.012
+
+
+def test_table1_coefficients_feed_the_interaction_matrix():
+    rows = {r[0]: [float(v) for v in r[1:]] for r in _golden_rows("table1_interaction.txt")}
+    assert tuple(rows["q"]) == tuple(synth.TABLE1_Q)
+    assert rows["gamma0_dot"][0] == synth.TABLE1_GAMMA0_DOT and rows["m"][0] == synth.TABLE1_M
+    q = tables.q_matrix(rows["q"])
+    # per row: 1 self, 2 coplanar, 1 collinear, 2 Hirth, 4 glissile, 2 Lomer
+    assert np.allclose(q.sum(axis=1), 0.122 + 2 * 0.122 + 0.657 + 2 * 0.084 + 4 * 0.137 + 2 * 0.118)
 
 
 def test_shear_modulus_is_resolved_111_110_shear_stiffness():
