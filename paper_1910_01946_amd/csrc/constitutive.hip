@@ -224,7 +224,7 @@ __device__ int newton(const Point& p, double n, double tol, int maxit, double* d
 
 // Shared set-up of a voxel: frame rotation, Fe0 = F_c Fp_n,c^{-1}, critical stresses.
 __device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev& M, int64_t v, int64_t nv,
-                                            const void* dF, bool dF_fp32, double* Rg, Point& p) {
+                                            const double* dF, double* Rg, Point& p) {
   const int g = args.gid[v];
 #pragma unroll
   for (int i = 0; i < 9; ++i) Rg[i] = args.grainR[9 * g + i];
@@ -232,8 +232,7 @@ __device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev&
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double f = args.F[i * nv + v];
-    if (dF) f += args.lam * (dF_fp32 ? (double)reinterpret_cast<const float*>(dF)[i * nv + v]
-                                      : reinterpret_cast<const double*>(dF)[i * nv + v]);
+    if (dF) f += args.lam * dF[i * nv + v];
     Fs[i] = f;
     Fps[i] = args.Fp_n[i * nv + v];
   }
@@ -276,7 +275,6 @@ __device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev&
 // stats[1] = failures, stats[2] = length of the work list.
 constexpr int kFastIters = 12;
 
-template <bool DF32>
 __global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
@@ -284,7 +282,7 @@ __global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
   const MatDev& M = *args.mat;
   double Rg[9];
   Point p;
-  setup_point(args, M, v, nv, args.dF, DF32, Rg, p);
+  setup_point(args, M, v, nv, args.dF, Rg, p);
   double dg[12];
 #pragma unroll
   for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
@@ -294,8 +292,7 @@ __global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
     double dFs[9], dFc[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      dFs[i] = DF32 ? (double)reinterpret_cast<const float*>(args.dF)[i * nv + v]
-                    : reinterpret_cast<const double*>(args.dF)[i * nv + v];
+      dFs[i] = args.dF[i * nv + v];
     to_crystal(Rg, dFs, dFc);
     const double s = args.lam - args.lam_base;
 #pragma unroll
@@ -321,7 +318,6 @@ __global__ void __launch_bounds__(64) k_slip_fast(ConstArgs args) {
 
 // Local solve, pass 2 (work-list voxels): continuation in the exponent from the warm
 // start, roots at n = 1, 2, 4, 8, 16, then Newton at n = 1/m.
-template <bool DF32>
 __global__ void __launch_bounds__(64) k_slip_slow(ConstArgs args) {
   const int count = args.stats[2];
   const int64_t nv = args.nvox;
@@ -330,7 +326,7 @@ __global__ void __launch_bounds__(64) k_slip_slow(ConstArgs args) {
     const MatDev& M = *args.mat;
     double Rg[9];
     Point p;
-    setup_point(args, M, v, nv, args.dF, DF32, Rg, p);
+    setup_point(args, M, v, nv, args.dF, Rg, p);
     double dg[12];
 #pragma unroll
     for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
@@ -360,7 +356,7 @@ __global__ void k_reset_stats(int32_t* stats) {
 }
 
 // Stress and consistent tangent at the converged slip increments.
-template <typename KT, bool DF32>
+template <typename KT>
 __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
@@ -370,7 +366,7 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
   Point p;
   ConstArgs a2 = args;
   a2.F_out = nullptr;
-  setup_point(a2, M, v, nv, args.dF, DF32, Rg, p);
+  setup_point(a2, M, v, nv, args.dF, Rg, p);
   double dg[12];
 #pragma unroll
   for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
@@ -525,18 +521,16 @@ void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st, LaunchTi
   hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, st, a.stats);
   {
     TimedLaunch t(timer, KF_SLIP_FAST, a.nvox, st);
-    if (fp32) launch(k_slip_fast<true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
-    else launch(k_slip_fast<false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    launch(k_slip_fast, dim3((unsigned)nb), dim3(bs), 0u, st, a);
   }
   {
     TimedLaunch t(timer, KF_SLIP_SLOW, a.nvox, st);
-    if (fp32) launch(k_slip_slow<true>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
-    else launch(k_slip_slow<false>, dim3((unsigned)nb_slow), dim3(bs), 0, st, a);
+    launch(k_slip_slow, dim3((unsigned)nb_slow), dim3(bs), 0u, st, a);
   }
   {
     TimedLaunch t(timer, KF_STRESS_TANGENT, a.nvox, st);
-    if (fp32) launch(k_stress_tangent<float, true>, dim3((unsigned)nb), dim3(bs), 0, st, a);
-    else launch(k_stress_tangent<double, false>, dim3((unsigned)nb), dim3(bs), 0, st, a);
+    if (fp32) launch(k_stress_tangent<float>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
+    else launch(k_stress_tangent<double>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
   }
 }
 

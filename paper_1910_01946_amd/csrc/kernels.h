@@ -26,7 +26,7 @@ struct ConstArgs {
   const double* grainR;          // 9 per grain, crystal -> sample
   const MatDev* mat;
   const double* F;               // evaluated at F + lam * dF (dF may be null)
-  const void* dF;                // same type as the tangent (double or float)
+  const double* dF;              // FP64 correction field, may be null
   double lam;
   double* F_out;                 // optional copy of the evaluated F
   const double* Fp_n;
@@ -57,6 +57,7 @@ struct CommitArgs {
   const double* rho_gnd;
 };
 
+// fp32_tangent: store K in FP32 (else FP64).  dF, when given, is an FP64 field.
 void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st, LaunchTimer* timer = nullptr);
 void launch_commit(const CommitArgs& a, hipStream_t st);
 void launch_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc, double* Ks,

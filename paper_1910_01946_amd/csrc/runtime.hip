@@ -369,8 +369,10 @@ struct EventTimer final : LaunchTimer {
   bool on(int f) const { return (mask >> f) & 1u; }
   hipEvent_t take() {
     if (pool.empty()) {
+      // device-scope release: no system-scope cache writeback at the kernel's end, which
+      // would otherwise lengthen the timed kernel itself
       hipEvent_t e;
-      HIPCHECK(hipEventCreate(&e));
+      HIPCHECK(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
       return e;
     }
     hipEvent_t e = pool.back();
@@ -460,6 +462,9 @@ struct RVE {
   hipStream_t stream = nullptr;   // each RVE runs on its own stream
   CGState* host_cg = nullptr;     // pinned copy of the CG scalars
   EventTimer timer;               // optional launch timing
+  Plan proj_plan;                 // FP64 projection of the Newton correction (mixed form)
+  DevBuf proj_spec, x64;
+  bool proj_ready = false;
   LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
     if (host_cg) (void)hipHostFree(host_cg);
@@ -576,8 +581,9 @@ struct LocalStats {
 
 // predict: start the local solve from dg + (lam - lam_base) d(dg)/dF : dF, where dg and
 // d(dg)/dF hold the converged solution of the previous call at F + lam_base dF.
-static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, const void* dF, double lam, double* F_out,
-                                   double dt, bool tangent, bool predict = false, double lam_base = 0.0) {
+static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, const double* dF, double lam,
+                                   double* F_out, double dt, bool tangent, bool predict = false,
+                                   double lam_base = 0.0) {
   ConstArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nvox = R.nvox;
@@ -613,6 +619,74 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   if (trace_on()) std::fprintf(stderr, "[rve] local solve: %d of %lld voxels on the continuation path, max it %d\n",
                                ls.slow, (long long)R.nvox, ls.max_iters);
   return ls;
+}
+
+// out = G(A) for a real FP64 field A (9 x nvox) with the zero-frequency rule of eq. 17:
+// component c keeps (its average - target_c) when keep_c = 1 and drops its average when
+// keep_c = 0.  out may alias A (A is read in full before out is written).
+static void project_field(const GridPlan& g, bool fp32, bool plane, void* spec, const double* A,
+                          const double* keep, const double* target, double* out, hipStream_t st) {
+  if (plane) {
+    PlaneArgs pa{PF_F64, A, spec};
+    launch_plane_fwd(g, fp32, pa, nullptr, st);
+  } else {
+    XFwdArgs xf;
+    std::memset(&xf, 0, sizeof(xf));
+    xf.mode = XF_FIELD64;
+    xf.in64 = A;
+    xf.spec = spec;
+    launch_xfwd(g, fp32, xf, st);
+    launch_yfft(g, fp32, spec, -1, nullptr, st);
+  }
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.op = MID_GREEN;
+  m.spec = spec;
+  for (int c = 0; c < 9; ++c) {
+    m.mask_keep[c] = keep[c];
+    m.dc_target[c] = target ? target[c] : 0.0;
+  }
+  m.inv_n = 1.0 / (double)g.nvox;
+  launch_mid(g, fp32, m, st);
+  if (plane) {
+    PlaneInvArgs pi;
+    std::memset(&pi, 0, sizeof(pi));
+    pi.mode = PI_OUT64;
+    pi.spec = spec;
+    pi.out64 = out;
+    launch_plane_inv(g, fp32, pi, st);
+  } else {
+    launch_yfft(g, fp32, spec, +1, nullptr, st);
+    XInvArgs xi;
+    std::memset(&xi, 0, sizeof(xi));
+    xi.mode = XI_OUT64;
+    xi.spec = spec;
+    xi.out64 = out;
+    launch_xinv(g, fp32, xi, st);
+  }
+}
+
+// The Newton correction applied to F, in FP64.  FP64 form: the CG solution itself.  Mixed
+// form: the FP32 CG solution carries components outside the range of G (its recurrences
+// accumulate FP32 roundings over hundreds of iterations), and F would drift away from a
+// compatible field; the correction is therefore widened to FP64 and projected again,
+// G(x) with the same zero-frequency rule (F-controlled averages stay fixed), so that
+// F - <F> stays a discrete gradient to FP64 rounding.
+static const double* newton_correction(RVE& R, Work& w, const void* x, const double* keep) {
+  if (!w.fp32) return static_cast<const double*>(x);
+  if (!R.proj_ready) {
+    build_plan(R.proj_plan, R.n, false);
+    R.proj_spec.alloc(tsize(false) * 2 * 9 * R.proj_plan.g.nspec);
+    R.x64.alloc(sizeof(double) * 9 * (size_t)R.nvox);
+    R.proj_ready = true;
+  }
+  double* x64 = R.x64.as<double>();
+  launch_widen(static_cast<const float*>(x), x64, 9 * R.nvox, R.stream);
+  const GridPlan& g = R.proj_plan.g;
+  project_field(g, false, plane_enabled() && plane_fits(g, false), R.proj_spec.p, x64, keep, nullptr, x64,
+                R.stream);
+  check_launch("newton correction");
+  return x64;
 }
 
 // projected apply of a stress-like FP64 field: r = -G(P - Pbar), p = r, x = 0; returns r.r
@@ -802,8 +876,8 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   return R.host_cg->iter;
 }
 
-static double rms_of(Ctx& C, RVE& R, Work& w, const void* f, int64_t n) {
-  const int nb = launch_sumsq(f, w.fp32, n, R.partial.as<double>(), R.stream);
+static double rms_of(Ctx& C, RVE& R, bool fp32, const void* f, int64_t n) {
+  const int nb = launch_sumsq(f, fp32, n, R.partial.as<double>(), R.stream);
   std::vector<double> part(nb);
   HIPCHECK(hipMemcpyAsync(part.data(), R.partial.p, sizeof(double) * nb, hipMemcpyDeviceToHost, R.stream));
   HIPCHECK(hipStreamSynchronize(R.stream));
@@ -909,7 +983,8 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     // A breakdown (negative curvature along p), a diverging residual or the iteration cap
     // ends CG with its current iterate, as truncated CG does; the residual line search
     // below decides whether that correction is usable.
-    const double dF = rms_of(C, R, w, x, 9 * nv);
+    const double* corr = newton_correction(R, w, x, keep);
+    const double dF = rms_of(C, R, false, corr, 9 * nv);
     if (!std::isfinite(dF)) {
       *why = "non-finite Newton correction";
       return RVE_ENOCONV;
@@ -918,8 +993,8 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     double lam = 1.0, res_try = 0.0, lam_base = 0.0;
     bool accepted = false;
     for (int ls_i = 0; ls_i <= C.opt.max_backtrack; ++ls_i) {
-      LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), x, lam, R.F_try.as<double>(), dt, true, true,
-                                       lam_base);
+      LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), corr, lam, R.F_try.as<double>(), dt, true,
+                                       true, lam_base);
       lam_base = lam;
       st.local_iters_max = std::max(st.local_iters_max, l2.max_iters);
       if (l2.failures == 0) {
@@ -1418,44 +1493,9 @@ int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, cons
     DevBuf spec;
     spec.alloc(tsize(fp32) * 2 * 9 * g.nspec);
     const bool plane = plane_enabled() && plane_fits(g, fp32);
-    XFwdArgs xf;
-    std::memset(&xf, 0, sizeof(xf));
-    xf.mode = XF_FIELD64;
-    xf.in64 = A;
-    xf.spec = spec.p;
-    if (plane) {
-      PlaneArgs pa{PF_F64, A, spec.p};
-      launch_plane_fwd(g, fp32, pa, nullptr, st);
-    } else {
-      launch_xfwd(g, fp32, xf, st);
-      launch_yfft(g, fp32, spec.p, -1, nullptr, st);
-    }
-    MidArgs m;
-    std::memset(&m, 0, sizeof(m));
-    m.op = MID_GREEN;
-    m.spec = spec.p;
-    for (int c = 0; c < 9; ++c) {
-      m.mask_keep[c] = mask[c] ? 0.0 : 1.0;
-      m.dc_target[c] = dc_target ? dc_target[c] : 0.0;
-    }
-    m.inv_n = 1.0 / (double)g.nvox;
-    launch_mid(g, fp32, m, st);
-    if (plane) {
-      PlaneInvArgs pi;
-      std::memset(&pi, 0, sizeof(pi));
-      pi.mode = PI_OUT64;
-      pi.spec = spec.p;
-      pi.out64 = out;
-      launch_plane_inv(g, fp32, pi, st);
-    } else {
-      launch_yfft(g, fp32, spec.p, +1, nullptr, st);
-      XInvArgs xi;
-      std::memset(&xi, 0, sizeof(xi));
-      xi.mode = XI_OUT64;
-      xi.spec = spec.p;
-      xi.out64 = out;
-      launch_xinv(g, fp32, xi, st);
-    }
+    double keep[9];
+    for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+    project_field(g, fp32, plane, spec.p, A, keep, dc_target, out, st);
     check_launch("project");
     HIPCHECK(hipStreamSynchronize(st));
     return RVE_OK;

@@ -132,6 +132,8 @@ void launch_cg_start(CGState* cg, const double* partial, int n, double tol2, int
 // and sum of squares of a T field.
 int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hipStream_t st);
 int launch_sumsq(const void* f, bool fp32, int64_t n, double* partial, hipStream_t st);
+// out[i] = (double)in[i], i < n
+void launch_widen(const float* in, double* out, int64_t n, hipStream_t st);
 
 // ---- plane path (x and y transforms of one component plane in LDS) ----------------
 enum PlaneSrc { PF_T = 0, PF_F64 = 1, PF_FPI = 2 };

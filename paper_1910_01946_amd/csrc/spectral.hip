@@ -615,6 +615,16 @@ int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hip
   return nb;
 }
 
+__global__ void k_widen(const float* in, double* out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (double)in[i];
+}
+
+void launch_widen(const float* in, double* out, int64_t n, hipStream_t st) {
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(256), 0, st, in, out, n);
+}
+
 int launch_sumsq(const void* f, bool fp32, int64_t n, double* partial, hipStream_t st) {
   int nb = (int)((n + 4095) / 4096);
   if (nb > 1024) nb = 1024;

@@ -59,3 +59,107 @@ def test_cu64_sgcp_at_8cubed_fp64_matches_oracle(lib):
         assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
     assert rel_norm(from_abi(h.field("nye")), o.alpha) < 1e-10
     assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd) < 1e-10
+
+
+def test_cu64_mixed_precision_macro_stress_within_1e4_of_oracle(lib):
+    """Mixed form (FP32 spectral path) at its performance tolerances against the FP64
+    oracle at tight tolerances: <P>_11 within 1e-4 relative at every increment."""
+    rves, path = synth.workload("cu64", n_override=8, n_inc_override=50)
+    o = solver.RVESolver(rves[0], newton_tol=1e-11, cg_tol=1e-10)
+    h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3, max_cg=3000, max_newton=150)
+    worst = 0.0
+    for k in range(1, 4):
+        print(f"mixed increment {k}", flush=True)
+        assert o.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)["converged"]
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        Po = o.macro()[0]
+        Pg = h.macro()[0]
+        worst = max(worst, abs(Pg[0] - Po[0]) / abs(Po[0]))
+    print("worst relative <P>_11 difference", worst, flush=True)
+    assert worst <= 1e-4
+
+
+def test_ragged_grid_fp64_matches_oracle(lib):
+    """A 10 x 6 x 12 grid (radix 2, 3, 5 transforms, odd plane sizes) through whole increments."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    rve = synth.voronoi_rve(311, (10, 6, 12), 4, 2e-6, mat)
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    o, h, out = _run_both(lib, rve, path, 2)
+    for Po, Pg, Fo, Fg in out:
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
+    assert rel_norm(from_abi(h.field("Fp")), o.Fp) < 1e-12
+    assert rel_norm(from_abi(h.field("nye")), o.alpha) < 1e-10
+    assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd) < 1e-10
+
+
+def test_save_load_replays_an_increment_bit_exactly(lib):
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    h = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    for k in (1, 2):
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+    state = h.save_state()
+    h.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)
+    first = {n: h.field(n) for n in ("F", "P", "Fp", "rho_ssd", "rho_gnd", "nye", "dg")}
+    P_first = h.macro()[0]
+    h.load_state(state)
+    P_loaded = h.macro()[0]
+    h.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)
+    for n, a in first.items():
+        assert np.array_equal(h.field(n), a), n
+    assert np.array_equal(h.macro()[0], P_first)
+    assert not np.array_equal(P_loaded, P_first)
+
+
+def test_failed_increment_leaves_state_unchanged(lib):
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    h = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    h.step(path.F_bar[1], path.mask, path.P_bar[1], path.dt)
+    before = {n: h.field(n) for n in ("F", "P", "Fp", "rho_ssd", "rho_gnd", "nye", "dg")}
+    P_before = h.macro()[0]
+    # one Newton iteration and no line search cannot meet a 1e-15 tolerance
+    h2 = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-15, cg_tol=1e-8, max_newton=1,
+                         max_backtrack=0)
+    h2.load_state(h.save_state())
+    with pytest.raises(lib.RVEError) as e:
+        h2.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)
+    assert e.value.code == -4 and e.value.stats[0]["status"] == -4
+    for n, a in before.items():
+        assert np.array_equal(h2.field(n), a), n
+    assert np.array_equal(h2.macro()[0], P_before)
+
+
+def test_batch_of_uneven_rves_equals_separate_handles(lib):
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    a = synth.voronoi_rve(401, (8, 8, 8), 5, 3e-6, mat)
+    b = synth.voronoi_rve(402, (6, 10, 4), 3, 2e-6, synth.material("Ni", rho0=1e11, c_gnd=1.0))
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    hb = lib.Homogenizer([a, b], precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    ha = lib.Homogenizer([a], precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    hs = lib.Homogenizer([b], precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    for k in (1, 2):
+        hb.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        ha.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        hs.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        assert np.array_equal(hb.macro(0)[0], ha.macro(0)[0])
+        assert np.array_equal(hb.macro(1)[0], hs.macro(0)[0])
+    assert np.array_equal(hb.field("rho_gnd", 1), hs.field("rho_gnd", 0))
+
+
+def test_kernel_timing_counts_live_launches(lib):
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3)
+    h.step(path.F_bar[1], path.mask, path.P_bar[1], path.dt)
+    h.timing_start(["cg_prep", "mid", "slip_fast"])
+    st = h.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)[0]
+    n_prep, ms_prep, b_prep = h.timing_read("cg_prep")
+    n_mid, ms_mid, b_mid = h.timing_read("mid")
+    n_fast, _, vox = h.timing_read("slip_fast")
+    assert n_fast >= 1 and vox == n_fast * rves[0].n_vox
+    # every CG iteration applies the operator once; residual evaluations add one z pass each
+    assert n_mid == st["cg_iters"] + st["residual_evals"]
+    assert st["cg_iters"] <= n_prep <= st["cg_iters"] + st["newton_iters"]
+    assert ms_mid > 0 and b_mid == n_mid * 2 * 9 * 2 * 4 * 5 * 8 * 8
+    assert h.timing_read("plane_fwd")[0] == 0          # not selected
+    h.timing_start([])
+    with pytest.raises(lib.RVEError):
+        lib.check(lib.lib().rve_timing_start(h.h, 1 << 9))        # unknown family bit
