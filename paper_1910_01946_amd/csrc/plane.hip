@@ -34,14 +34,37 @@ __device__ __forceinline__ double block_sum2(double v, double* sh) {
   return s;
 }
 
+// Sum of n per-block partials in a fixed order (thread t adds t, t + blockDim, ...), the
+// same in every block that calls it with the same blockDim; every thread gets the sum.
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
+  __shared__ double total;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+  s = block_sum2(s, red);
+  if (threadIdx.x == 0) total = s;
+  __syncthreads();
+  const double t = total;
+  __syncthreads();
+  return t;
+}
+
 // Threads per plane block: the plane transforms are a chain of dependent LDS stages, so
 // more threads per plane (fewer points each) shorten the chain.
 constexpr int kPlaneThreads = 512;
 
 template <typename T, int SRC, int PPT>
-__global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, const CGState* cg) {
+__global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, CGState* cg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (cg && cg->done) return;
+  __shared__ double red[8];
+  if (cg) {
+    if (cg->done) return;
+    // beta step of this iteration (one block; the others only read the stop flag, and a
+    // block that already sees it set leaves its plane untransformed, which is never used)
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      const double rr = sum_partials(a.rr_partial, a.n_rr, red);
+      if (threadIdx.x == 0) cg_beta_update(cg, rr, a.it == 0);
+    }
+  }
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
   const int npair = (ny + 1) / 2, nyp = ny + 1;
@@ -202,13 +225,29 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   }
 }
 
-// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame).
+// alpha step of the previous iteration, x += alpha p, r -= alpha q (iteration > 0),
+// partial r.r, y = K : r (sample frame).
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
-  if (a.cg->done) return;
-  const bool upd = a.cg->iter > 0;
-  const double alpha = a.cg->alpha;
+  CGState* cg = a.cg;
+  if (cg->done) return;
+  const bool upd = a.it > 0;
+  double alpha = 0.0;
+  if (upd) {
+    // alpha step of the previous iteration, taken identically by every block from the
+    // inverse pass's p.q partials; block 0 records it
+    const double pq = sum_partials(a.pq_partial, a.n_pq, red);
+    const bool ok = pq > 0.0 && pq < 1e300;
+    alpha = ok ? cg->rr / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cg->pq = pq;
+      cg->alpha = alpha;
+      cg->iter = a.it;
+      if (!ok) cg->done = 2;  // breakdown: the operator is not positive along p
+    }
+    if (!ok) return;
+  }
   T* X = reinterpret_cast<T*>(a.x);
   T* Rr = reinterpret_cast<T*>(a.r);
   const T* P = reinterpret_cast<const T*>(a.p);
@@ -329,13 +368,13 @@ hipError_t set_plane_lds_limits(int bytes) {
 }
 
 template <typename T, int SRC, int PPT>
-static void fwd_launch(const GridPlan& g, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
+static void fwd_launch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
   launch(k_plane_fwd<T, SRC, PPT>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a, cg);
 }
 
 template <typename T, int SRC>
-static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
+static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const int ppt = plane_ppt(g);
   if (ppt <= 5) fwd_launch<T, SRC, 5>(g, a, cg, st);
   else if (ppt <= 9) fwd_launch<T, SRC, 9>(g, a, cg, st);
@@ -343,7 +382,7 @@ static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, const CGState* c
   else fwd_launch<T, SRC, 33>(g, a, cg, st);
 }
 
-void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CGState* cg, hipStream_t st) {
+void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   if (fp32) {
     if (a.src == PF_T) fwd_dispatch<float, PF_T>(g, a, cg, st);
     else if (a.src == PF_F64) fwd_dispatch<float, PF_F64>(g, a, cg, st);
@@ -386,7 +425,7 @@ int plane_blocks(const GridPlan& g) { return 9 * g.nz; }
 
 int prep_blocks(const GridPlan& g) {
   const int64_t nb = (g.nvox + 255) / 256;
-  return (int)std::min<int64_t>(nb, 2048);
+  return (int)std::min<int64_t>(nb, 1024);
 }
 
 void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st) {

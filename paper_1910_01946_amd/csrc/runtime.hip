@@ -822,7 +822,11 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pr.y = w.y.p;
   pr.cg = cg;
   pr.partial = part;
+  pr.pq_partial = part + 2048;
+  pr.n_pq = plane_blocks(g);
   PlaneArgs pa{PF_T, w.y.p, w.spec.p};
+  pa.rr_partial = part;
+  pa.n_rr = prep_blocks(g);
   PlaneInvArgs pi;
   std::memset(&pi, 0, sizeof(pi));
   pi.mode = PI_CG;
@@ -837,12 +841,15 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   for (;;) {
     if (R.host_cg->done) break;
     for (int i = 0; i < chunk && w.plane; ++i, ++issued) {
+      // prep takes the previous iteration's alpha step, the forward pass this iteration's
+      // beta step (in their own blocks; no separate scalar launches)
       R.timer.tag = issued;
+      pr.it = issued;
+      pa.it = issued;
       {
         TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, issued == 0), R.stream);
         launch_cg_prep(g, w.fp32, pr, R.stream);
       }
-      launch_cg_beta(cg, part, prep_blocks(g), R.stream);
       {
         TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_cg(g, w.fp32), R.stream);
         launch_plane_fwd(g, w.fp32, pa, cg, R.stream);
@@ -855,7 +862,6 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
         TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_cg(g, w.fp32), R.stream);
         launch_plane_inv(g, w.fp32, pi, R.stream);
       }
-      launch_cg_alpha(cg, part + 2048, plane_blocks(g), R.stream);
     }
     R.timer.tag = -1;
     for (int i = 0; i < chunk && !w.plane; ++i) {

@@ -96,9 +96,9 @@ void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGSta
 // ---- CG scalar updates (device side) ----------------------------------------------
 // beta step, after r.r of the updated residual: beta = r.r / previous r.r; stop when
 // r.r <= tol2 r0.r0 (1), when it grows past 1e4 r0.r0 or is not finite (3), or at the
-// iteration cap (4).
-__device__ inline void cg_beta_update(CGState* cg, double rr) {
-  cg->beta = (cg->iter == 0) ? 0.0 : rr / cg->rr;
+// iteration cap (4).  first: the first iteration of the solve (beta = 0).
+__device__ inline void cg_beta_update(CGState* cg, double rr, bool first) {
+  cg->beta = first ? 0.0 : rr / cg->rr;
   cg->rr = rr;
   if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
   else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;
@@ -143,6 +143,11 @@ struct PlaneArgs {
   int src;                     // PF_T: field of type T; PF_F64: FP64 field; PF_FPI: FP64 Fp - I
   const void* in;              // 9 x nvox
   void* spec;                  // out: half spectrum
+  // CG iteration (with a CGState): block 0 sums the r.r partials of k_cg_prep and takes the
+  // beta step before the inverse pass reads beta
+  const double* rr_partial;
+  int n_rr;
+  int it;                      // iteration index within the solve (0 = first)
 };
 
 struct PlaneInvArgs {
@@ -168,6 +173,9 @@ struct PrepArgs {
   void* y;                     // out: K : r (T)
   CGState* cg;
   double* partial;             // per-block r.r
+  const double* pq_partial;    // per-block p.q of the previous iteration's inverse pass
+  int n_pq;
+  int it;                      // iteration index within the solve (0 = first)
 };
 
 bool plane_fits(const GridPlan& g, bool fp32);
@@ -177,7 +185,7 @@ hipError_t set_spectral_lds_limits(int bytes);
 hipError_t set_plane_lds_limits(int bytes);
 int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
-void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, const CGState* cg, hipStream_t st);
+void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
 void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st);
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,

@@ -437,7 +437,7 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
 __global__ void k_cg_beta(CGState* cg, const double* partial, int n) {
   if (cg->done) return;
   const double rr = reduce_partials(partial, n);
-  if (threadIdx.x == 0) cg_beta_update(cg, rr);
+  if (threadIdx.x == 0) cg_beta_update(cg, rr, cg->iter == 0);
 }
 
 __global__ void k_cg_alpha(CGState* cg, const double* partial, int n) {

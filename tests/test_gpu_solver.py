@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import solver
+from oracle import nye, solver
 from tests.gpu_util import from_abi, rel_norm
 
 pytestmark = pytest.mark.gpu
@@ -84,12 +84,25 @@ def test_ragged_grid_fp64_matches_oracle(lib):
     mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
     rve = synth.voronoi_rve(311, (10, 6, 12), 4, 2e-6, mat)
     path = synth.uniaxial_tension(0.05, 50, 1e-4)
-    o, h, out = _run_both(lib, rve, path, 2)
+    o, h, out = _run_both(lib, rve, path, 2, newton_tol=1e-13, cg_tol=1e-12)
     for Po, Pg, Fo, Fg in out:
         assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
-    assert rel_norm(from_abi(h.field("Fp")), o.Fp) < 1e-12
-    assert rel_norm(from_abi(h.field("nye")), o.alpha) < 1e-10
-    assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd) < 1e-10
+    Fp = from_abi(h.field("Fp"))
+    d_fp = rel_norm(Fp, o.Fp)
+    assert d_fp < 1e-12
+    # The Nye tensor differentiates Fp - I (here ~2e-3 of |Fp|), and the difference of two
+    # solutions converged to a tolerance is rougher than the field itself: the
+    # whole-increment alpha and rho_GND are held to 10 x the measured Fp difference
+    # relative to |Fp - I|.  The curl and GND kernels are held to 1e-12 on the GPU's own Fp.
+    fp_dev = np.linalg.norm(o.Fp - np.eye(3)) / np.linalg.norm(o.Fp)
+    bound = 10.0 * d_fp / fp_dev
+    print("Fp difference", d_fp, "Fp - I relative size", fp_dev, "field bound", bound, flush=True)
+    assert rel_norm(from_abi(h.field("nye")), o.alpha) < bound
+    assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd) < bound
+    alpha, _, rho = nye.gnd_from_fp(Fp.reshape(rve.grain_of_voxel.shape + (3, 3)), rve.voxel_size,
+                                    rve.grain_of_voxel, rve.quats, rve.material.burgers)
+    assert rel_norm(from_abi(h.field("nye")), alpha.reshape(-1, 3, 3)) < 1e-12
+    assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), rho.reshape(-1, 12)) < 1e-12
 
 
 def test_save_load_replays_an_increment_bit_exactly(lib):
