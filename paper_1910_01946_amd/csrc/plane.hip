@@ -225,29 +225,14 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   }
 }
 
-// alpha step of the previous iteration, x += alpha p, r -= alpha q (iteration > 0),
-// partial r.r, y = K : r (sample frame).
+// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame).
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
-  CGState* cg = a.cg;
+  const CGState* cg = a.cg;
   if (cg->done) return;
-  const bool upd = a.it > 0;
-  double alpha = 0.0;
-  if (upd) {
-    // alpha step of the previous iteration, taken identically by every block from the
-    // inverse pass's p.q partials; block 0 records it
-    const double pq = sum_partials(a.pq_partial, a.n_pq, red);
-    const bool ok = pq > 0.0 && pq < 1e300;
-    alpha = ok ? cg->rr / pq : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      cg->pq = pq;
-      cg->alpha = alpha;
-      cg->iter = a.it;
-      if (!ok) cg->done = 2;  // breakdown: the operator is not positive along p
-    }
-    if (!ok) return;
-  }
+  const bool upd = cg->iter > 0;
+  const double alpha = cg->alpha;
   T* X = reinterpret_cast<T*>(a.x);
   T* Rr = reinterpret_cast<T*>(a.r);
   const T* P = reinterpret_cast<const T*>(a.p);

@@ -822,8 +822,6 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pr.y = w.y.p;
   pr.cg = cg;
   pr.partial = part;
-  pr.pq_partial = part + 2048;
-  pr.n_pq = plane_blocks(g);
   PlaneArgs pa{PF_T, w.y.p, w.spec.p};
   pa.rr_partial = part;
   pa.n_rr = prep_blocks(g);
@@ -841,10 +839,9 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   for (;;) {
     if (R.host_cg->done) break;
     for (int i = 0; i < chunk && w.plane; ++i, ++issued) {
-      // prep takes the previous iteration's alpha step, the forward pass this iteration's
-      // beta step (in their own blocks; no separate scalar launches)
+      // the forward pass takes this iteration's beta step in its first block (no separate
+      // launch); the alpha step, which every block of the next prep needs, has its own
       R.timer.tag = issued;
-      pr.it = issued;
       pa.it = issued;
       {
         TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, issued == 0), R.stream);
@@ -862,6 +859,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
         TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_cg(g, w.fp32), R.stream);
         launch_plane_inv(g, w.fp32, pi, R.stream);
       }
+      launch_cg_alpha(cg, part + 2048, plane_blocks(g), R.stream);
     }
     R.timer.tag = -1;
     for (int i = 0; i < chunk && !w.plane; ++i) {

@@ -173,9 +173,6 @@ struct PrepArgs {
   void* y;                     // out: K : r (T)
   CGState* cg;
   double* partial;             // per-block r.r
-  const double* pq_partial;    // per-block p.q of the previous iteration's inverse pass
-  int n_pq;
-  int it;                      // iteration index within the solve (0 = first)
 };
 
 bool plane_fits(const GridPlan& g, bool fp32);

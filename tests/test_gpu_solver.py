@@ -89,7 +89,9 @@ def test_ragged_grid_fp64_matches_oracle(lib):
         assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
     Fp = from_abi(h.field("Fp"))
     d_fp = rel_norm(Fp, o.Fp)
-    assert d_fp < 1e-12
+    # the solves stop at a correction rms of 1e-13; FP64 rounding through a stiff plastic
+    # tangent leaves the two converged fields ~1e-12 apart
+    assert d_fp < 1e-11
     # The Nye tensor differentiates Fp - I (here ~2e-3 of |Fp|), and the difference of two
     # solutions converged to a tolerance is rougher than the field itself: the
     # whole-increment alpha and rho_GND are held to 10 x the measured Fp difference
