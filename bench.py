@@ -240,11 +240,14 @@ def main():
               "newton_cg_fallback_per_increment": main_leg["iters"], "P11_last": float(main_leg["P"][0][0])}
     if prec == lib.RVE_MIXED and not args.no_fp64_compare:
         ref = run_leg(lib, rves, path, lib.RVE_FP64, W, K, args)
-        rel = max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(main_leg["P"], ref["P"]))
+        per_rve = [abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(main_leg["P"], ref["P"])]
+        rel = max(per_rve)
         config["fp64_form"] = {"value": ref["value"], "ms_per_step": 1e3 * ref["T"] / K,
                                "newton_cg_fallback_per_increment": ref["iters"],
                                "speedup_mixed_over_fp64": main_leg["value"] / ref["value"],
                                "P11_rel_diff_mixed_vs_fp64": rel}
+        if len(per_rve) > 1:
+            config["fp64_form"]["P11_rel_diff_per_rve"] = [float("%.3g" % v) for v in per_rve]
     line = {
         "metric": METRIC,
         "value": main_leg["value"],

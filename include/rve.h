@@ -77,8 +77,8 @@ typedef struct {
   int32_t precision;     /* RVE_FP64: every step in FP64.  RVE_MIXED: FFTs, projection,
                             conjugate-gradient vectors and the tangent copy in FP32; the
                             constitutive update, F, Fp and the macroscopic averages in FP64 */
-  double newton_tol;     /* stop an increment once the rms of the applied correction dF is
-                            below this value                                                 */
+  double newton_tol;     /* stop an increment once the rms of the full Newton correction dF
+                            is below this value (that correction is then applied whole)      */
   double cg_tol;         /* relative residual of the conjugate-gradient solve of eq. 18      */
   int32_t max_newton;    /* Newton iterations per increment                                  */
   int32_t max_cg;        /* CG iterations per Newton iteration                               */
@@ -97,7 +97,7 @@ typedef struct {
   int32_t line_search_cuts;  /* step halvings in the residual line search                       */
   int32_t local_iters_max;   /* largest local Newton iteration count of any voxel               */
   double res_norm;           /* rms of the final projected residual G(P - P_bar), Pa           */
-  double dF_norm;            /* rms of the last applied correction                              */
+  double dF_norm;            /* rms of the last full Newton correction                          */
   double voxel_iterations;   /* nvox * (residual_evals + cg_iters)                              */
   int32_t fp64_fallback;     /* RVE_MIXED: 1 if the FP32 attempt failed and the increment was
                                 solved with the FP64 spectral path                              */

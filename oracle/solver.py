@@ -134,7 +134,9 @@ class RVESolver:
                     b_try = -self.project(out_try["P"], mask, P_bar)
                     stats["residuals"] += 1
                     res_try = float(np.sqrt(np.mean(b_try * b_try)))
-                    if res_try <= res or lam * np.sqrt(np.mean(dF * dF)) <= self.newton_tol:
+                    # a full correction below the tolerance is taken without a decrease
+                    # test (the residual is then at its rounding floor)
+                    if res_try <= res or (lam == 1.0 and np.sqrt(np.mean(dF * dF)) <= self.newton_tol):
                         break
                 lam *= 0.5
             else:
@@ -142,10 +144,13 @@ class RVESolver:
                 return self._finish(stats, t0)
             stats["line_search_cuts"] = stats.get("line_search_cuts", 0) + _ls
             F, out, b, res = F_try, out_try, b_try, res_try
-            dF_rms = lam * float(np.sqrt(np.mean(dF * dF)))
+            dF_full = float(np.sqrt(np.mean(dF * dF)))
+            dF_rms = lam * dF_full
             stats["dF_norm"] = dF_rms
             stats["res_norm"] = res
-            if dF_rms <= self.newton_tol:
+            # converged when the full Newton correction, not a line-search fraction of
+            # it, is below the tolerance
+            if lam == 1.0 and dF_full <= self.newton_tol:
                 stats["converged"] = True
                 break
         self._finish(stats, t0)

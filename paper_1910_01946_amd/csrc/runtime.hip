@@ -1005,7 +1005,9 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
         const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
         st.residual_evals++;
         res_try = std::sqrt(rr_t / n9);
-        if (std::isfinite(res_try) && (res_try <= res || lam * dF <= C.opt.newton_tol)) {
+        // a full correction below the tolerance is applied without a decrease test (the
+        // residual is then at its rounding floor); otherwise the residual must not grow
+        if (std::isfinite(res_try) && (res_try <= res || (lam == 1.0 && dF <= C.opt.newton_tol))) {
           accepted = true;
           break;
         }
@@ -1025,9 +1027,10 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     std::swap(R.F_work.p, R.F_try.p);
     std::swap(x, xo);
     res = res_try;
-    st.dF_norm = lam * dF;
+    st.dF_norm = dF;
     st.res_norm = res;
-    if (lam * dF <= C.opt.newton_tol) return RVE_OK;
+    // converged when the full Newton correction (not a line-search fraction of it) is small
+    if (lam == 1.0 && dF <= C.opt.newton_tol) return RVE_OK;
   }
   *why = "Newton did not converge within max_newton";
   return RVE_ENOCONV;
