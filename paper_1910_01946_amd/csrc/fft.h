@@ -7,7 +7,8 @@
 // for every j in [0, n/R).  Each stage reads all of its inputs into registers, then a
 // barrier, then writes all outputs: the transform runs in place in one LDS buffer.
 //
-// Lines are addressed as base(l) + e * estride with base(l) = (l / L1) * S1 + (l % L1) * S0.
+// Lines are addressed as base(l) + e * estride with base(l) = (l / L1) * S1 + (l % L1) * S0,
+// or, with estride 0, as base(l) + padded(e).
 #pragma once
 
 #include "common.h"
@@ -20,10 +21,19 @@ struct AxisPlan {
   int rad[8];
 };
 
+// LDS slot of element e of a contiguous line with one pad slot after every 8 elements:
+// radix-8 stages read 8 consecutive elements of each of several lines and write elements
+// 8 apart; with this padding and a line stride of 72 (for 64-point lines) both patterns
+// fall on distinct LDS banks.
+__device__ __forceinline__ int padded(int e) { return e + (e >> 3); }
+// line stride for n padded elements
+__host__ __device__ constexpr int padded_len(int n) { return n + (n + 7) / 8; }
+
 struct LineLayout {
   int nlines;
-  int L1, S1, S0, estride;
+  int L1, S1, S0, estride;  // estride 0: contiguous padded lines (element e at padded(e))
   __device__ __forceinline__ int base(int l) const { return (l / L1) * S1 + (l % L1) * S0; }
+  __device__ __forceinline__ int elem(int e) const { return estride ? e * estride : padded(e); }
 };
 
 template <typename T>
@@ -120,7 +130,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int
       const int l = idx / M, j = idx - l * M;
       const int base = L.base(l);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * M) * L.estride];
+      for (int r = 0; r < R; ++r) v[b][r] = buf[base + L.elem(j + r * M)];
     }
   }
   __syncthreads();
@@ -142,7 +152,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int
       const int out = (j / Ns) * Ns * R + k;
       const int base = L.base(l);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + (out + r * Ns) * L.estride] = v[b][r];
+      for (int r = 0; r < R; ++r) buf[base + L.elem(out + r * Ns)] = v[b][r];
     }
   }
   __syncthreads();

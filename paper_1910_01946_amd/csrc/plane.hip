@@ -67,10 +67,11 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   }
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
-  const int npair = (ny + 1) / 2, nyp = ny + 1;
+  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded())
+  const int npair = (ny + 1) / 2, SA = padded_len(nx), SB = padded_len(ny);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* B = A + npair * nx;
-  cplx<T>* twx = B + nxh * nyp;
+  cplx<T>* B = A + npair * SA;
+  cplx<T>* twx = B + nxh * SB;
   cplx<T>* twy = twx + nx;
   const int64_t nv = g.nvox;
   const int64_t base = (int64_t)c * nv + (int64_t)z * ny * nx;
@@ -97,29 +98,29 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
       const int idx = b0 + u * nthr;
       if (idx < nload) {
         const int y = idx / nx, x = idx - y * nx;
-        cplx<T>& e = A[(y >> 1) * nx + x];
+        cplx<T>& e = A[(y >> 1) * SA + padded(x)];
         if (y & 1) e.y = val[u];
         else e.x = val[u];
       }
     }
   }
   __syncthreads();
-  fft_lines<T, PPT>(A, LineLayout{npair, 1, nx, 0, 1}, g.ax, twx, (T)-1);
+  fft_lines<T, PPT>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)-1);
   for (int idx = tid; idx < npair * nxh; idx += nthr) {
     const int p = idx / nxh, k = idx - p * nxh;
-    const cplx<T> Zk = A[p * nx + k];
-    const cplx<T> Zm = A[p * nx + (nx - k) % nx];
+    const cplx<T> Zk = A[p * SA + padded(k)];
+    const cplx<T> Zm = A[p * SA + padded((nx - k) % nx)];
     const T h = (T)0.5;
-    B[k * nyp + 2 * p] = cmk(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
-    if (2 * p + 1 < ny) B[k * nyp + 2 * p + 1] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
+    B[k * SB + padded(2 * p)] = cmk(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
+    if (2 * p + 1 < ny) B[k * SB + padded(2 * p + 1)] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, nyp, 0, 1}, g.ay, twy, (T)-1);
+  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0}, g.ay, twy, (T)-1);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   const int64_t sbase = ((int64_t)c * nz + z) * ny * nxh;
   for (int idx = tid; idx < ny * nxh; idx += nthr) {
     const int ky = idx / nxh, kx = idx - ky * nxh;
-    spec[sbase + idx] = B[kx * nyp + ky];
+    spec[sbase + idx] = B[kx * SB + padded(ky)];
   }
 }
 
@@ -130,10 +131,11 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   if (MODE == PI_CG && a.cg->done) return;
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
-  const int npair = (ny + 1) / 2, nyp = ny + 1;
+  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded())
+  const int npair = (ny + 1) / 2, SA = padded_len(nx), SB = padded_len(ny);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* B = A + npair * nx;
-  cplx<T>* twx = B + nxh * nyp;
+  cplx<T>* B = A + npair * SA;
+  cplx<T>* twx = B + nxh * SB;
   cplx<T>* twy = twx + nx;
   const int64_t nv = g.nvox;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -153,26 +155,26 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
       const int idx = b0 + u * nthr;
       if (idx < ny * nxh) {
         const int ky = idx / nxh, kx = idx - ky * nxh;
-        B[kx * nyp + ky] = val[u];
+        B[kx * SB + padded(ky)] = val[u];
       }
     }
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, nyp, 0, 1}, g.ay, twy, (T)1);
+  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0}, g.ay, twy, (T)1);
   for (int idx = tid; idx < npair * nx; idx += nthr) {
     const int p = idx / nx, k = idx - p * nx;
     const bool hi = k >= nxh;
     const int kk = hi ? nx - k : k;
-    cplx<T> Av = B[kk * nyp + 2 * p];
-    cplx<T> Bv = (2 * p + 1 < ny) ? B[kk * nyp + 2 * p + 1] : cmk((T)0, (T)0);
+    cplx<T> Av = B[kk * SB + padded(2 * p)];
+    cplx<T> Bv = (2 * p + 1 < ny) ? B[kk * SB + padded(2 * p + 1)] : cmk((T)0, (T)0);
     if (hi) {
       Av.y = -Av.y;
       Bv.y = -Bv.y;
     }
-    A[p * nx + k] = cmk(Av.x - Bv.y, Av.y + Bv.x);
+    A[p * SA + padded(k)] = cmk(Av.x - Bv.y, Av.y + Bv.x);
   }
   __syncthreads();
-  fft_lines<T, PPT>(A, LineLayout{npair, 1, nx, 0, 1}, g.ax, twx, (T)1);
+  fft_lines<T, PPT>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)1);
   const int64_t base = (int64_t)c * nv + (int64_t)z * ny * nx;
   double acc = 0.0;
   const double beta = (MODE == PI_CG) ? a.cg->beta : 0.0;
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
       const int idx = b0 + u * nthr;
       if (idx < ny * nx) {
         const int y = idx / nx, x = idx - y * nx;
-        const cplx<T> e = A[(y >> 1) * nx + x];
+        const cplx<T> e = A[(y >> 1) * SA + padded(x)];
         w[u] = (double)((y & 1) ? e.y : e.x);
         if (MODE == PI_CG) {
           const int64_t o = base + idx;
@@ -307,7 +309,7 @@ __global__ void k_gnd(int64_t nv, const double* nye, const int32_t* gid, const d
 static size_t plane_lds(const GridPlan& g, bool fp32) {
   const size_t cs = fp32 ? 8 : 16;
   const size_t npair = (g.ny + 1) / 2;
-  return cs * (npair * g.nx + (size_t)g.nxh * (g.ny + 1) + g.nx + g.ny);
+  return cs * (npair * padded_len(g.nx) + (size_t)g.nxh * padded_len(g.ny) + g.nx + g.ny);
 }
 
 static int plane_ppt(const GridPlan& g) {
@@ -315,7 +317,7 @@ static int plane_ppt(const GridPlan& g) {
   return (npts + kPlaneThreads - 1) / kPlaneThreads;
 }
 
-bool plane_fits(const GridPlan& g, bool fp32) { return plane_lds(g, fp32) <= 150 * 1024 && plane_ppt(g) <= 33; }
+bool plane_fits(const GridPlan& g, bool fp32) { return plane_lds(g, fp32) <= 159 * 1024 && plane_ppt(g) <= 33; }
 
 // bytes: LDS per work-group of the device; the kernel's static LDS is taken off it.
 template <typename K>

@@ -264,10 +264,9 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
   g.ly = std::min(ly, ny_even);
   g.ty = std::min(16, g.nxh);
   if (g.ny * g.ty > 16 * 256) g.ty = (16 * 256) / g.ny;
-  // kx columns per z-pass block: nz * tz about 256 (9 points per thread; more than 2 blocks
-  // per compute unit at 64^3), never more than 18 points per thread
+  // kx columns per z-pass block: nz * tz <= 256, i.e. at most 9 points per thread of a
+  // 256-thread block (the z-pass transform is compiled for that bound)
   g.tz = std::max(1, std::min(g.nxh, 256 / g.nz));
-  g.tz = std::max(1, std::min(g.tz, (18 * 256) / (9 * g.nz)));
   if (const char* e = std::getenv("RVE_TZ")) g.tz = std::max(1, std::min(g.tz, std::atoi(e)));
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
@@ -775,6 +774,8 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   {
     CGState s = *R.host_cg;
     s.iter = 0;
+    s.rr_best = s.rr0;
+    s.it_best = 0;
     s.done = (s.rr0 > 0.0 && C.opt.max_cg > 0) ? 0 : 1;
     s.tol2 = C.opt.cg_tol * C.opt.cg_tol;
     s.max_iter = C.opt.max_cg;
@@ -984,9 +985,9 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     const int ncg = run_cg(C, R, w, x, keep, done);
     const CGState cg_end = *R.host_cg;
     st.cg_iters += ncg;
-    // A breakdown (negative curvature along p), a diverging residual or the iteration cap
-    // ends CG with its current iterate, as truncated CG does; the residual line search
-    // below decides whether that correction is usable.
+    // A breakdown (negative curvature along p), a diverging or stalled residual or the
+    // iteration cap ends CG with its current iterate, as truncated CG does; the residual
+    // line search below decides whether that correction is usable.
     const double* corr = newton_correction(R, w, x, keep);
     const double dF = rms_of(C, R, false, corr, 9 * nv);
     if (!std::isfinite(dF)) {

@@ -40,11 +40,18 @@ struct CGState {
   double pq;
   double alpha, beta;
   double tol2;     // stop when rr <= tol2 * rr0
+  double rr_best;  // smallest r.r so far that was at most a quarter of the previous best
   int32_t iter;    // completed operator applications
-  int32_t done;    // 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 diverging (r.r > 1e4 r0.r0), 4 max_iter
+  int32_t done;    // 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 diverging (r.r > 1e4 r0.r0),
+                   // 4 max_iter, 5 stalled (|r| not halved within kCgStall iterations)
   int32_t max_iter;
-  int32_t pad;
+  int32_t it_best; // iteration of rr_best
 };
+
+// A solve whose residual norm has not halved for this many iterations has reached the
+// rounding floor of the operator (the consistent tangent is not symmetric, and CG on a
+// right-hand side at that floor need not converge): it stops with its current iterate.
+constexpr int kCgStall = 500;
 
 enum XFwdMode { XF_FIELD64 = 0, XF_CG = 1, XF_FP_MINUS_I = 2 };
 enum XInvMode { XI_RESID = 0, XI_CG = 1, XI_NYE = 2, XI_OUT64 = 3 };
@@ -95,14 +102,20 @@ void launch_xfwd(const GridPlan& g, bool fp32, const XFwdArgs& a, hipStream_t st
 void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGState* cg, hipStream_t st);
 // ---- CG scalar updates (device side) ----------------------------------------------
 // beta step, after r.r of the updated residual: beta = r.r / previous r.r; stop when
-// r.r <= tol2 r0.r0 (1), when it grows past 1e4 r0.r0 or is not finite (3), or at the
-// iteration cap (4).  first: the first iteration of the solve (beta = 0).
+// r.r <= tol2 r0.r0 (1), when it grows past 1e4 r0.r0 or is not finite (3), at the
+// iteration cap (4), or when |r| has stalled (5).  first: the first iteration of the
+// solve (beta = 0).
 __device__ inline void cg_beta_update(CGState* cg, double rr, bool first) {
   cg->beta = first ? 0.0 : rr / cg->rr;
   cg->rr = rr;
+  if (first || rr <= 0.25 * cg->rr_best) {
+    cg->rr_best = rr;
+    cg->it_best = cg->iter;
+  }
   if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
   else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;
   else if (cg->iter >= cg->max_iter) cg->done = 4;
+  else if (cg->iter - cg->it_best >= kCgStall) cg->done = 5;
 }
 
 // alpha step, after p.q: alpha = r.r / p.q; a non-positive (or non-finite) p.q is a

@@ -171,7 +171,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   if (a.cg && a.cg->done) return;
-  const int ny = g.ny, nz = g.nz, nxh = g.nxh, tz = g.tz, tzp = g.tz + 1;
+  const int ny = g.ny, nz = g.nz, nxh = g.nxh, tz = g.tz, SZ = padded_len(nz);
   // XCD-aware order: consecutive hardware block ids are dealt to the 8 XCDs in turn; each
   // XCD takes a contiguous range of (ky, kx tile) so that the cache lines shared by
   // neighbouring tiles and rows are fetched and written back through a single L2.
@@ -183,7 +183,8 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   const int ky = logical / ntile, kx0 = (logical % ntile) * tz;
   const int tid = threadIdx.x, nthr = blockDim.x;
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
-  cplx<T>* twz = buf + 9 * nz * tzp;
+  // one contiguous padded z line per (component, kx column): line c * tz + j
+  cplx<T>* twz = buf + 9 * tz * SZ;
   load_twiddles(twz, g.twz, nz);
   const int nload = 9 * nz * tz;
   // 8 independent loads in flight per thread before the LDS writes
@@ -205,13 +206,13 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
       if (idx < nload) {
         const int j = idx % tz, t = idx / tz;
         const int zz = t % nz, c = t / nz;
-        buf[(c * nz + zz) * tzp + j] = val[u];
+        buf[(c * tz + j) * SZ + padded(zz)] = val[u];
       }
     }
   }
   __syncthreads();
-  LineLayout L{9 * tz, tz, nz * tzp, 1, tzp};
-  fft_lines<T, 18>(buf, L, g.az, twz, (T)-1);
+  LineLayout L{9 * tz, 1, SZ, 0, 0};
+  fft_lines<T, 9>(buf, L, g.az, twz, (T)-1);
   const cplx<double>* Ex = reinterpret_cast<const cplx<double>*>(g.Ex);
   const cplx<double>* Ey = reinterpret_cast<const cplx<double>*>(g.Ey);
   const cplx<double>* Ez = reinterpret_cast<const cplx<double>*>(g.Ez);
@@ -221,7 +222,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     cplx<double> A[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const cplx<T> e = buf[(c * nz + kz) * tzp + j];
+      const cplx<T> e = buf[(c * tz + j) * SZ + padded(kz)];
       A[c] = cmk((double)e.x, (double)e.y);
     }
     // modified frequency vector of the rotated scheme (eq. A.4):
@@ -274,14 +275,14 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
       }
     }
 #pragma unroll
-    for (int c = 0; c < 9; ++c) buf[(c * nz + kz) * tzp + j] = cmk((T)out[c].x, (T)out[c].y);
+    for (int c = 0; c < 9; ++c) buf[(c * tz + j) * SZ + padded(kz)] = cmk((T)out[c].x, (T)out[c].y);
   }
   __syncthreads();
-  fft_lines<T, 18>(buf, L, g.az, twz, (T)1);
+  fft_lines<T, 9>(buf, L, g.az, twz, (T)1);
   for (int idx = tid; idx < nload; idx += nthr) {
     const int j = idx % tz, t = idx / tz;
     const int zz = t % nz, c = t / nz;
-    if (kx0 + j < nxh) spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j] = buf[(c * nz + zz) * tzp + j];
+    if (kx0 + j < nxh) spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j] = buf[(c * tz + j) * SZ + padded(zz)];
   }
 }
 
@@ -427,6 +428,8 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
     cg->rr0 = rr;
     cg->tol2 = tol2;
     cg->iter = 0;
+    cg->rr_best = rr;
+    cg->it_best = 0;
     cg->max_iter = max_iter;
     cg->alpha = 0.0;
     cg->beta = 0.0;
@@ -562,7 +565,7 @@ int mid_blocks(const GridPlan& g) {
 
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) {
   const dim3 grid(mid_blocks(g));
-  const size_t sh = ((size_t)9 * g.nz * (g.tz + 1) + g.nz) * (fp32 ? 8 : 16);
+  const size_t sh = ((size_t)9 * g.tz * padded_len(g.nz) + g.nz) * (fp32 ? 8 : 16);
   if (fp32) {
     if (a.op == MID_GREEN) {
       launch(k_mid<float, MID_GREEN>, grid, dim3(256), (uint32_t)sh, st, g, a);
