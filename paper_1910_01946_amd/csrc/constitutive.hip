@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
       for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];   // + e_k (x) H_l.
       const int col = 3 * kk + ll;
 #pragma unroll
-      for (int r = 0; r < 9; ++r) Kout[(int64_t)(r * 9 + col) * nv + v] = (KT)dP[r];
+      for (int r = 0; r < 9; ++r) Kout[tangent_index<KT>(r * 9 + col, v, nv, args.k_grouped)] = (KT)dP[r];
     }
   }
 }

@@ -43,8 +43,25 @@ struct ConstArgs {
                                  // frame, index (9a + 3k + l) * nvox + v); written with K, may be null
   double lam_base;               // dg (and dgdF) were computed at F + lam_base * dF
   int32_t predict;               // 1: the first pass starts from dg + (lam - lam_base) dgdF : dF_c
-  int32_t pad;
+  int32_t k_grouped;             // K layout: 0 entry-major (e * nvox + v), 1 grouped (see tangent_index)
 };
+
+// Layout of the tangent copy used by the conjugate-gradient kernels.  FP64: the 81
+// entries of a voxel in 16-byte groups of W = 2 consecutive entries, group-major over
+// voxels, so that one lane reads two entries with one vector load while a wavefront still
+// reads contiguous memory (fewer memory instructions in flight per voxel).  FP32: entry-
+// major (W = 1); 16-byte groups there need the whole tangent in registers at once, which
+// costs more occupancy than the wider loads gain.
+template <typename KT>
+struct TangentGroups {
+  static constexpr int W = sizeof(KT) == 8 ? 2 : 1;
+  static constexpr int G = (81 + W - 1) / W;  // groups per voxel (last one padded)
+};
+template <typename KT>
+__host__ __device__ __forceinline__ int64_t tangent_index(int e, int64_t v, int64_t nv, bool grouped) {
+  constexpr int W = TangentGroups<KT>::W;
+  return grouped ? ((int64_t)(e / W) * nv + v) * W + (e % W) : (int64_t)e * nv + v;
+}
 
 struct CommitArgs {
   int64_t nvox;

@@ -16,6 +16,7 @@
 #include "spectral.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rve {
 
@@ -239,7 +240,10 @@ __global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
   T* Rr = reinterpret_cast<T*>(a.r);
   const T* P = reinterpret_cast<const T*>(a.p);
   const T* Q = reinterpret_cast<const T*>(a.q);
-  const T* K = reinterpret_cast<const T*>(a.K);
+  // tangent in the grouped layout: G vector loads of W entries per voxel
+  using KG = TangentGroups<T>;
+  using KV = typename std::conditional<sizeof(T) == 4, float, double2>::type;
+  const KV* K = reinterpret_cast<const KV*>(a.K);
   T* Y = reinterpret_cast<T*>(a.y);
   double acc = 0.0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
@@ -264,12 +268,31 @@ __global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) Rg[i] = a.grainR[9 * gi + i];
     to_crystal(Rg, rs, rc);
+    if constexpr (KG::W == 1) {
+      // FP32: entry-major, loads interleaved with the products (keeps occupancy)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      double s = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) s += (double)K[(int64_t)(i * 9 + j) * nv + v] * rc[j];
-      yc[i] = s;
+        for (int j = 0; j < 9; ++j) s += (double)K[(int64_t)(i * 9 + j) * nv + v] * rc[j];
+        yc[i] = s;
+      }
+    } else {
+      // FP64: two entries per 16-byte load
+      T kv[KG::G * KG::W];
+#pragma unroll
+      for (int gq = 0; gq < KG::G; ++gq) {
+        const KV q = K[(int64_t)gq * nv + v];
+        kv[2 * gq] = q.x;
+        kv[2 * gq + 1] = q.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) s += (double)kv[i * 9 + j] * rc[j];
+        yc[i] = s;
+      }
     }
     to_sample(Rg, yc, ys);
 #pragma unroll

@@ -497,7 +497,9 @@ static Work& work(RVE& R, bool fp32) {
     build_plan(w.plan, R.n, fp32);
     const int64_t nv = R.nvox;
     const size_t ts = tsize(fp32);
-    w.K.alloc(ts * 81 * nv);
+    // grouped layout: G groups of W entries per voxel (see tangent_index)
+    w.K.alloc(ts * (fp32 ? TangentGroups<float>::G * TangentGroups<float>::W
+                         : TangentGroups<double>::G * TangentGroups<double>::W) * nv);
     w.xa.alloc(ts * 9 * nv);
     w.xb.alloc(ts * 9 * nv);
     w.r.alloc(ts * 9 * nv);
@@ -599,6 +601,7 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.dg = R.dg.as<double>();
   a.P = R.P_work.as<double>();
   a.K = tangent ? w.K.p : nullptr;
+  a.k_grouped = 1;
   a.dt = dt;
   a.stats = R.blk.as<int32_t>();
   a.work = R.blk.as<int32_t>() + 4;

@@ -97,7 +97,7 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
         for (int i = 0; i < 9; ++i) {
           double s = 0.0;
 #pragma unroll
-          for (int j = 0; j < 9; ++j) s += (double)K[(int64_t)(i * 9 + j) * nv + v] * pc[j];
+          for (int j = 0; j < 9; ++j) s += (double)K[tangent_index<T>(i * 9 + j, v, nv, true)] * pc[j];
           yc[i] = s;
         }
         to_sample(Rg, yc, ys);
