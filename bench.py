@@ -40,14 +40,17 @@ METRIC = "voxel-iterations/s per MI355X, mixed-prec+batched vs plain FP64 at 1e-
 
 # kernel families of the timing interface: kernel names (as profilers list them) and the
 # source files whose change invalidates stored counter readings
+_CONST_SRC = ["constitutive.hip", "kernels.h", "timing.h", "common.h"]
+_PLANE_SRC = ["plane.hip", "spectral.h", "fft.h", "kernels.h", "timing.h", "common.h"]
+_MID_SRC = ["spectral.hip", "spectral.h", "fft.h", "kernels.h", "timing.h", "common.h"]
 FAMILY_KERNELS = {
-    "slip_fast": ("k_slip_fast", ["constitutive.hip", "kernels.h", "common.h"]),
-    "slip_slow": ("k_slip_slow", ["constitutive.hip", "kernels.h", "common.h"]),
-    "stress_tangent": ("k_stress_tangent", ["constitutive.hip", "kernels.h", "common.h"]),
-    "cg_prep": ("k_cg_prep", ["plane.hip", "spectral.h", "common.h"]),
-    "plane_fwd": ("k_plane_fwd", ["plane.hip", "spectral.h", "fft.h", "common.h"]),
-    "mid": ("k_mid", ["spectral.hip", "spectral.h", "fft.h", "common.h"]),
-    "plane_inv": ("k_plane_inv", ["plane.hip", "spectral.h", "fft.h", "common.h"]),
+    "slip_fast": ("k_slip_fast", _CONST_SRC),
+    "slip_slow": ("k_slip_slow", _CONST_SRC),
+    "stress_tangent": ("k_stress_tangent", _CONST_SRC),
+    "cg_prep": ("k_cg_prep", _PLANE_SRC),
+    "plane_fwd": ("k_plane_fwd", _PLANE_SRC),
+    "mid": ("k_mid", _MID_SRC),
+    "plane_inv": ("k_plane_inv", _PLANE_SRC),
 }
 SPECTRAL = ("cg_prep", "plane_fwd", "mid", "plane_inv")
 
