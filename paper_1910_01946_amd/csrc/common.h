@@ -45,6 +45,33 @@ template <typename T>
 __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) { return cmk(-s * a.y, s * a.x); }
 
 // ------------------------------------------------------------------------------------
+// Division by a divisor fixed for a launch (grid extents, tile widths, FFT stage sizes).
+// gfx950 has no integer divide instruction.  A power of two d = 2^s divides by a shift;
+// any other d by one multiply-high with m = ceil(2^32 / d): with x = q d + f (0 <= f < d)
+// and m = 2^32 / d + e (0 <= e < 1), x m / 2^32 = q + f / d + x e / 2^32, whose floor is
+// q while x d < 2^32 (f / d <= 1 - 1/d).  Every use divides an index below 2^17 by a
+// divisor below 2^9.
+// ------------------------------------------------------------------------------------
+struct FastDiv {
+  uint32_t m;   // 0: power of two
+  int32_t sh;   // log2 d when m == 0
+};
+__host__ __device__ inline FastDiv make_fastdiv(int d) {
+  FastDiv f;
+  if ((d & (d - 1)) == 0) {
+    f.m = 0u;
+    f.sh = d > 1 ? __builtin_ctz((unsigned)d) : 0;
+  } else {
+    f.m = 0xFFFFFFFFu / (uint32_t)d + 1u;
+    f.sh = 0;
+  }
+  return f;
+}
+__device__ __forceinline__ int fdiv(int x, FastDiv f) {
+  return f.m ? (int)__umulhi((uint32_t)x, f.m) : (x >> f.sh);
+}
+
+// ------------------------------------------------------------------------------------
 // FCC slip systems {111}<110> in the crystal frame, unit vectors (plane-major order).
 // s: slip direction, m: plane normal.
 // ------------------------------------------------------------------------------------

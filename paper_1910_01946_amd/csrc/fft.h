@@ -19,6 +19,7 @@ struct AxisPlan {
   int n;
   int nrad;
   int rad[8];
+  uint32_t code;  // rad[s] in bits 4s..4s+3 (read by shifts: no indexed access on the device)
 };
 
 // LDS slot of element e of a contiguous line with one pad slot after every 8 elements:
@@ -32,7 +33,11 @@ __host__ __device__ constexpr int padded_len(int n) { return n + (n + 7) / 8; }
 struct LineLayout {
   int nlines;
   int L1, S1, S0, estride;  // estride 0: contiguous padded lines (element e at padded(e))
-  __device__ __forceinline__ int base(int l) const { return (l / L1) * S1 + (l % L1) * S0; }
+  FastDiv dL1;              // division by L1; the zero value divides by 1
+  __device__ __forceinline__ int base(int l) const {
+    const int q = fdiv(l, dL1);
+    return q * S1 + (l - q * L1) * S0;
+  }
   __device__ __forceinline__ int elem(int e) const { return estride ? e * estride : padded(e); }
 };
 
@@ -113,21 +118,24 @@ __device__ __forceinline__ void dftR(cplx<T>* v, T sign) {
   else dft8(v, sign);
 }
 
-// One Stockham stage over all lines.  MAXB bounds the butterflies per thread.
+// One Stockham stage over all lines.  MAXB bounds the butterflies per thread.  The
+// twiddle exponent k r n / (Ns R) stays below n (k < Ns, r < R) and the output slot
+// (j / Ns) Ns R + k equals (j - k) R + k, so the only divisions are by M and Ns.
 template <typename T, int R, int MAXB>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int n, int Ns,
                                           const cplx<T>* __restrict__ tw, T sign) {
   const int M = n / R;
+  const FastDiv dM = make_fastdiv(M), dNs = make_fastdiv(Ns);
   const int total = L.nlines * M;
   const int nthr = blockDim.x * blockDim.y;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int twstep = n / (Ns * R);
+  const int twstep = fdiv(M, dNs);  // n / (Ns R)
   cplx<T> v[MAXB][R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int idx = tid + b * nthr;
     if (idx < total) {
-      const int l = idx / M, j = idx - l * M;
+      const int l = fdiv(idx, dM), j = idx - l * M;
       const int base = L.base(l);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[base + L.elem(j + r * M)];
@@ -138,19 +146,19 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int
   for (int b = 0; b < MAXB; ++b) {
     const int idx = tid + b * nthr;
     if (idx < total) {
-      const int l = idx / M, j = idx - l * M;
-      const int k = j % Ns;
+      const int l = fdiv(idx, dM), j = idx - l * M;
+      const int base = L.base(l);
+      const int k = j - fdiv(j, dNs) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cplx<T> w = tw[(k * r * twstep) % n];
+          cplx<T> w = tw[k * r * twstep];
           if (sign > 0) w.y = -w.y;
           v[b][r] = cmul(v[b][r], w);
         }
       }
       dftR<T, R>(v[b], sign);
-      const int out = (j / Ns) * Ns * R + k;
-      const int base = L.base(l);
+      const int out = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[base + L.elem(out + r * Ns)] = v[b][r];
     }
@@ -161,11 +169,11 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int
 // In-place transform of every line; sign = -1 forward, +1 inverse (unnormalised).
 // PPT: upper bound of (lines * n) / threads, fixed at compile time.
 template <typename T, int PPT>
-__device__ void fft_lines(cplx<T>* buf, const LineLayout& L, const AxisPlan& ap, const cplx<T>* __restrict__ tw,
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, const LineLayout& L, const AxisPlan& ap, const cplx<T>* __restrict__ tw,
                           T sign) {
   int Ns = 1;
   for (int s = 0; s < ap.nrad; ++s) {
-    const int R = ap.rad[s];
+    const int R = (ap.code >> (4 * s)) & 15;
     switch (R) {
       case 8: fft_stage<T, 8, (PPT + 7) / 8>(buf, L, ap.n, Ns, tw, sign); break;
       case 4: fft_stage<T, 4, (PPT + 3) / 4>(buf, L, ap.n, Ns, tw, sign); break;

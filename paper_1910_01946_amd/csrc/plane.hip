@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
     for (int u = 0; u < 8; ++u) {
       const int idx = b0 + u * nthr;
       if (idx < nload) {
-        const int y = idx / nx, x = idx - y * nx;
+        const int y = fdiv(idx, g.fnx), x = idx - y * nx;
         cplx<T>& e = A[(y >> 1) * SA + padded(x)];
         if (y & 1) e.y = val[u];
         else e.x = val[u];
@@ -108,9 +108,9 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   __syncthreads();
   fft_lines<T, PPT>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)-1);
   for (int idx = tid; idx < npair * nxh; idx += nthr) {
-    const int p = idx / nxh, k = idx - p * nxh;
+    const int p = fdiv(idx, g.fnxh), k = idx - p * nxh;
     const cplx<T> Zk = A[p * SA + padded(k)];
-    const cplx<T> Zm = A[p * SA + padded((nx - k) % nx)];
+    const cplx<T> Zm = A[p * SA + padded(k == 0 ? 0 : nx - k)];
     const T h = (T)0.5;
     B[k * SB + padded(2 * p)] = cmk(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
     if (2 * p + 1 < ny) B[k * SB + padded(2 * p + 1)] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   const int64_t sbase = ((int64_t)c * nz + z) * ny * nxh;
   for (int idx = tid; idx < ny * nxh; idx += nthr) {
-    const int ky = idx / nxh, kx = idx - ky * nxh;
+    const int ky = fdiv(idx, g.fnxh), kx = idx - ky * nxh;
     spec[sbase + idx] = B[kx * SB + padded(ky)];
   }
 }
@@ -149,13 +149,14 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = b0 + u * nthr;
+      val[u] = cmk((T)0, (T)0);
       if (idx < ny * nxh) val[u] = spec[sbase + idx];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = b0 + u * nthr;
       if (idx < ny * nxh) {
-        const int ky = idx / nxh, kx = idx - ky * nxh;
+        const int ky = fdiv(idx, g.fnxh), kx = idx - ky * nxh;
         B[kx * SB + padded(ky)] = val[u];
       }
     }
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   __syncthreads();
   fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0}, g.ay, twy, (T)1);
   for (int idx = tid; idx < npair * nx; idx += nthr) {
-    const int p = idx / nx, k = idx - p * nx;
+    const int p = fdiv(idx, g.fnx), k = idx - p * nx;
     const bool hi = k >= nxh;
     const int kk = hi ? nx - k : k;
     cplx<T> Av = B[kk * SB + padded(2 * p)];
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
     for (int u = 0; u < 4; ++u) {
       const int idx = b0 + u * nthr;
       if (idx < ny * nx) {
-        const int y = idx / nx, x = idx - y * nx;
+        const int y = fdiv(idx, g.fnx), x = idx - y * nx;
         const cplx<T> e = A[(y >> 1) * SA + padded(x)];
         w[u] = (double)((y & 1) ? e.y : e.x);
         if (MODE == PI_CG) {

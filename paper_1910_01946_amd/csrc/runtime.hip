@@ -214,6 +214,8 @@ static AxisPlan make_axis(int n) {
       m /= r;
     }
   if (m != 1) throw Error(RVE_EINVAL, "grid sizes must have prime factors 2, 3 and 5 only");
+  a.code = 0;
+  for (int s = 0; s < a.nrad; ++s) a.code |= (uint32_t)a.rad[s] << (4 * s);
   return a;
 }
 
@@ -268,6 +270,10 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
   // 256-thread block (the z-pass transform is compiled for that bound)
   g.tz = std::max(1, std::min(g.nxh, 256 / g.nz));
   if (const char* e = std::getenv("RVE_TZ")) g.tz = std::max(1, std::min(g.tz, std::atoi(e)));
+  g.fnx = make_fastdiv(g.nx);
+  g.fnxh = make_fastdiv(g.nxh);
+  g.fnz = make_fastdiv(g.nz);
+  g.ftz = make_fastdiv(g.tz);
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
     const int m = n[d];

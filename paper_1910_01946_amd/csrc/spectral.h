@@ -20,6 +20,7 @@ struct GridPlan {
   int ly;            // rows per block in the x passes (even)
   int ty;            // kx columns per block in the y passes
   int tz;            // kx columns per block in the z pass
+  FastDiv fnx, fnxh, fnz, ftz;  // divisions by nx, nxh, nz, tz
 };
 
 // Device-resident scalars of the conjugate-gradient loop (FP64).

@@ -155,7 +155,7 @@ __global__ void k_yfft(GridPlan g, void* spec_, int sign, const CGState* cg) {
     buf[y * typ + j] = (kx0 + j < nxh) ? spec[base + (int64_t)y * nxh + j] : cmk((T)0, (T)0);
   }
   __syncthreads();
-  LineLayout L{ty, ty, 0, 1, typ};
+  LineLayout L{ty, ty, 0, 1, typ, make_fastdiv(ty)};
   fft_lines<T, 16>(buf, L, g.ay, reinterpret_cast<const cplx<T>*>(g.twy), (T)sign);
   for (int idx = tid; idx < ny * ty; idx += nthr) {
     const int y = idx / ty, j = idx - y * ty;
@@ -195,8 +195,8 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
       const int idx = b0 + u * nthr;
       val[u] = cmk((T)0, (T)0);
       if (idx < nload) {
-        const int j = idx % tz, t = idx / tz;
-        const int zz = t % nz, c = t / nz;
+        const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+        const int c = fdiv(t, g.fnz), zz = t - c * nz;
         if (kx0 + j < nxh) val[u] = spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j];
       }
     }
@@ -204,8 +204,8 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     for (int u = 0; u < 8; ++u) {
       const int idx = b0 + u * nthr;
       if (idx < nload) {
-        const int j = idx % tz, t = idx / tz;
-        const int zz = t % nz, c = t / nz;
+        const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+        const int c = fdiv(t, g.fnz), zz = t - c * nz;
         buf[(c * tz + j) * SZ + padded(zz)] = val[u];
       }
     }
@@ -217,14 +217,8 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   const cplx<double>* Ey = reinterpret_cast<const cplx<double>*>(g.Ey);
   const cplx<double>* Ez = reinterpret_cast<const cplx<double>*>(g.Ez);
   for (int idx = tid; idx < nz * tz; idx += nthr) {
-    const int j = idx % tz, kz = idx / tz, kx = kx0 + j;
+    const int kz = fdiv(idx, g.ftz), j = idx - kz * tz, kx = kx0 + j;
     if (kx >= nxh) continue;
-    cplx<double> A[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const cplx<T> e = buf[(c * tz + j) * SZ + padded(kz)];
-      A[c] = cmk((double)e.x, (double)e.y);
-    }
     // modified frequency vector of the rotated scheme (eq. A.4):
     // k_i = 1/4 (-i)(E_i - 1) prod_{j != i} (1 + E_j)
     const cplx<double> ex = Ex[kx], ey = Ey[ky], ez = Ez[kz];
@@ -234,54 +228,58 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     kv[0] = cmuli(cscale(cmul(mx, cmul(py, pz)), 0.25), -1.0);
     kv[1] = cmuli(cscale(cmul(my, cmul(px, pz)), 0.25), -1.0);
     kv[2] = cmuli(cscale(cmul(mz, cmul(px, py)), 0.25), -1.0);
-    cplx<double> out[9];
-    if (OP == MID_GREEN) {
-      if (kx == 0 && ky == 0 && kz == 0) {
-        const double nvox = (double)g.nvox;
-#pragma unroll
-        for (int c = 0; c < 9; ++c)
-          out[c] = cscale(cmk(A[c].x - nvox * a.dc_target[c], A[c].y), a.mask_keep[c] * a.inv_n);
-      } else {
-        const double k2 = kv[0].x * kv[0].x + kv[0].y * kv[0].y + kv[1].x * kv[1].x + kv[1].y * kv[1].y +
-                          kv[2].x * kv[2].x + kv[2].y * kv[2].y;
-        if (k2 == 0.0) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) out[c] = cmk(0.0, 0.0);
-        } else {
-          const double s = a.inv_n / k2;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            // u_i = sum_l A_il conj(k_l) / |k|^2 ; (G:A)_ij = u_i k_j
-            cplx<double> u = cmk(0.0, 0.0);
-#pragma unroll
-            for (int l = 0; l < 3; ++l) u = cadd(u, cmulc(A[3 * i + l], kv[l]));
-            u = cscale(u, s);
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) out[3 * i + jj] = cmul(u, kv[jj]);
-          }
-        }
-      }
-    } else {
+    const bool dc = kx == 0 && ky == 0 && kz == 0;
+    const double k2 = kv[0].x * kv[0].x + kv[0].y * kv[0].y + kv[1].x * kv[1].x + kv[1].y * kv[1].y +
+                      kv[2].x * kv[2].x + kv[2].y * kv[2].y;
+    cplx<double> ik[3];
+    if (OP != MID_GREEN) {
       // alpha_ij = eps_jml (i k_m / h) Fp_il
       const double s = a.inv_h * a.inv_n;
-      cplx<double> ik[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) ik[m] = cscale(cmuli(kv[m], 1.0), s);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        out[3 * i + 0] = csub(cmul(ik[1], A[3 * i + 2]), cmul(ik[2], A[3 * i + 1]));
-        out[3 * i + 1] = csub(cmul(ik[2], A[3 * i + 0]), cmul(ik[0], A[3 * i + 2]));
-        out[3 * i + 2] = csub(cmul(ik[0], A[3 * i + 1]), cmul(ik[1], A[3 * i + 0]));
-      }
     }
+    // both operators map row i of the input to row i of the output: one row at a time, in place
 #pragma unroll
-    for (int c = 0; c < 9; ++c) buf[(c * tz + j) * SZ + padded(kz)] = cmk((T)out[c].x, (T)out[c].y);
+    for (int i = 0; i < 3; ++i) {
+      cplx<double> A[3], out[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const cplx<T> e = buf[((3 * i + l) * tz + j) * SZ + padded(kz)];
+        A[l] = cmk((double)e.x, (double)e.y);
+      }
+      if (OP == MID_GREEN) {
+        if (dc) {
+          const double nvox = (double)g.nvox;
+#pragma unroll
+          for (int l = 0; l < 3; ++l)
+            out[l] = cscale(cmk(A[l].x - nvox * a.dc_target[3 * i + l], A[l].y), a.mask_keep[3 * i + l] * a.inv_n);
+        } else if (k2 == 0.0) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) out[l] = cmk(0.0, 0.0);
+        } else {
+          // u_i = sum_l A_il conj(k_l) / |k|^2 ; (G:A)_ij = u_i k_j
+          const double s = a.inv_n / k2;
+          cplx<double> u = cmk(0.0, 0.0);
+#pragma unroll
+          for (int l = 0; l < 3; ++l) u = cadd(u, cmulc(A[l], kv[l]));
+          u = cscale(u, s);
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) out[jj] = cmul(u, kv[jj]);
+        }
+      } else {
+        out[0] = csub(cmul(ik[1], A[2]), cmul(ik[2], A[1]));
+        out[1] = csub(cmul(ik[2], A[0]), cmul(ik[0], A[2]));
+        out[2] = csub(cmul(ik[0], A[1]), cmul(ik[1], A[0]));
+      }
+#pragma unroll
+      for (int l = 0; l < 3; ++l) buf[((3 * i + l) * tz + j) * SZ + padded(kz)] = cmk((T)out[l].x, (T)out[l].y);
+    }
   }
   __syncthreads();
   fft_lines<T, 9>(buf, L, g.az, twz, (T)1);
   for (int idx = tid; idx < nload; idx += nthr) {
-    const int j = idx % tz, t = idx / tz;
-    const int zz = t % nz, c = t / nz;
+    const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+    const int c = fdiv(t, g.fnz), zz = t - c * nz;
     if (kx0 + j < nxh) spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j] = buf[(c * tz + j) * SZ + padded(zz)];
   }
 }
