@@ -466,6 +466,8 @@ struct RVE {
   int64_t fp64_fallbacks = 0;
   hipStream_t stream = nullptr;   // each RVE runs on its own stream
   CGState* host_cg = nullptr;     // pinned copy of the CG scalars
+  CGState* host_poll = nullptr;   // two pinned snapshots of the CG scalars, read by the chunk loop
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   EventTimer timer;               // optional launch timing
   Plan proj_plan;                 // FP64 projection of the Newton correction (mixed form)
   DevBuf proj_spec, x64;
@@ -473,6 +475,9 @@ struct RVE {
   LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
     if (host_cg) (void)hipHostFree(host_cg);
+    if (host_poll) (void)hipHostFree(host_poll);
+    for (hipEvent_t e : poll_ev)
+      if (e) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
   }
   bool have_prev = false;
@@ -565,6 +570,8 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   R.dgdF.alloc(sizeof(float) * 108 * (size_t)nv);
   HIPCHECK(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));
   HIPCHECK(hipHostMalloc((void**)&R.host_cg, sizeof(CGState), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&R.host_poll, 2 * sizeof(CGState), hipHostMallocDefault));
+  for (hipEvent_t& e : R.poll_ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   Work& w = work(R, C.fp32);
   R.cg.alloc(sizeof(CGState));
   HIPCHECK(hipMemset(R.cg.p, 0, sizeof(CGState)));
@@ -846,8 +853,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pi.partial = part + 2048;
   const int chunk = 4;
   int issued = 0;  // CG iterations launched so far
-  for (;;) {
-    if (R.host_cg->done) break;
+  auto issue_chunk = [&]() {
     for (int i = 0; i < chunk && w.plane; ++i, ++issued) {
       // the forward pass takes this iteration's beta step in its first block (no separate
       // launch); the alpha step, which every block of the next prep needs, has its own
@@ -882,9 +888,27 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
       launch_cg_alpha(cg, part, nb, R.stream);
     }
     check_launch("cg");
-    HIPCHECK(hipMemcpyAsync(R.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
-    HIPCHECK(hipStreamSynchronize(R.stream));
+  };
+  // snapshot of the CG scalars after the chunk just issued, into pinned slot s
+  auto snapshot = [&](int s) {
+    HIPCHECK(hipMemcpyAsync(&R.host_poll[s], cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
+    HIPCHECK(hipEventRecord(R.poll_ev[s], R.stream));
+  };
+  if (!R.host_cg->done) {
+    // the stop flag of chunk c - 1 is read while chunk c is already queued, so the GPU
+    // never waits for the host; once the flag is set, the kernels of the chunk in flight
+    // read it and return at once
+    issue_chunk();
+    snapshot(0);
+    for (int c = 1;; ++c) {
+      issue_chunk();
+      snapshot(c & 1);
+      HIPCHECK(hipEventSynchronize(R.poll_ev[(c - 1) & 1]));
+      if (R.host_poll[(c - 1) & 1].done) break;
+    }
   }
+  HIPCHECK(hipMemcpyAsync(R.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
+  HIPCHECK(hipStreamSynchronize(R.stream));
   R.timer.resolve(R.host_cg->iter);
   done_code = R.host_cg->done;
   return R.host_cg->iter;
