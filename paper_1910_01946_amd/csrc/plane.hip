@@ -229,15 +229,28 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   }
 }
 
-// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame).
+// xb = x over the grid-stride range of this thread
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
+__device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) XB[c * nv + v] = X[c * nv + v];
+  }
+}
+
+// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame); the
+// iterate is copied to xbest first when the previous iteration set a new best r.r.
+template <typename T>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
   if (cg->done) return;
   const bool upd = cg->iter > 0;
+  // the previous iteration's iterate set a new best r.r: keep a copy before it moves
+  const bool keep = upd && cg->it_best == cg->iter - 1;
   const double alpha = cg->alpha;
   T* X = reinterpret_cast<T*>(a.x);
+  T* XB = reinterpret_cast<T*>(a.xbest);
   T* Rr = reinterpret_cast<T*>(a.r);
   const T* P = reinterpret_cast<const T*>(a.p);
   const T* Q = reinterpret_cast<const T*>(a.q);
@@ -247,6 +260,7 @@ __global__ void __launch_bounds__(256) k_cg_prep(int64_t nv, PrepArgs a) {
   const KV* K = reinterpret_cast<const KV*>(a.K);
   T* Y = reinterpret_cast<T*>(a.y);
   double acc = 0.0;
+  if (keep) copy_iterate(X, XB, nv);
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
     double rs[9];
     if (upd) {

@@ -341,7 +341,7 @@ struct Work {
   bool fp32 = false;
   bool ready = false;
   Plan plan;
-  DevBuf K, xa, xb, r, p, q, y, spec;
+  DevBuf K, xa, xb, xbest, r, p, q, y, spec;
   bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
 };
 
@@ -513,6 +513,7 @@ static Work& work(RVE& R, bool fp32) {
                          : TangentGroups<double>::G * TangentGroups<double>::W) * nv);
     w.xa.alloc(ts * 9 * nv);
     w.xb.alloc(ts * 9 * nv);
+    w.xbest.alloc(ts * 9 * nv);
     w.r.alloc(ts * 9 * nv);
     w.p.alloc(ts * 9 * nv);
     w.q.alloc(ts * 9 * nv);
@@ -805,6 +806,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   xf.gid = R.d_gid.as<int32_t>();
   xf.grainR = R.d_R.as<double>();
   xf.x = x;
+  xf.xbest = w.xbest.p;
   xf.r = w.r.p;
   xf.p = w.p.p;
   xf.q = w.q.p;
@@ -833,6 +835,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pr.gid = R.d_gid.as<int32_t>();
   pr.grainR = R.d_R.as<double>();
   pr.x = x;
+  pr.xbest = w.xbest.p;
   pr.r = w.r.p;
   pr.p = w.p.p;
   pr.q = w.q.p;
@@ -1019,9 +1022,15 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     const CGState cg_end = *R.host_cg;
     st.cg_iters += ncg;
     // A breakdown (negative curvature along p), a diverging or stalled residual or the
-    // iteration cap ends CG with its current iterate, as truncated CG does; the residual
-    // line search below decides whether that correction is usable.
-    const double* corr = newton_correction(R, w, x, keep);
+    // iteration cap ends CG early, as in truncated CG.  The correction is then the iterate
+    // with the smallest r.r seen, if any iterate improved on the start (the current one
+    // unless r.r has grown since; after a converged solve the current r.r is the smallest),
+    // and the residual line search below decides whether it is usable.  Only a solve that
+    // converged, or stalled at its rounding floor, can end the Newton iteration: a small
+    // correction from a broken-down solve says nothing about the residual.
+    const bool cg_ok = done == 1 || done == 5;
+    const bool use_best = done != 1 && cg_end.it_best > 0 && cg_end.rr > cg_end.rr_best;
+    const double* corr = newton_correction(R, w, use_best ? w.xbest.p : x, keep);
     const double dF = rms_of(C, R, false, corr, 9 * nv);
     if (!std::isfinite(dF)) {
       *why = "non-finite Newton correction";
@@ -1041,7 +1050,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
         res_try = std::sqrt(rr_t / n9);
         // a full correction below the tolerance is applied without a decrease test (the
         // residual is then at its rounding floor); otherwise the residual must not grow
-        if (std::isfinite(res_try) && (res_try <= res || (lam == 1.0 && dF <= C.opt.newton_tol))) {
+        if (std::isfinite(res_try) && (res_try <= res || (lam == 1.0 && dF <= C.opt.newton_tol && cg_ok))) {
           accepted = true;
           break;
         }
@@ -1051,8 +1060,8 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     }
     if (trace_on())
       std::fprintf(stderr,
-                   "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e) |dF| %.3e lam %.4g res %.4e -> %.4e%s local_it %d\n",
-                   it + 1, ncg, done, cg_end.rr / cg_end.rr0, dF, lam, res, res_try,
+                   "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e%s) |dF| %.3e lam %.4g res %.4e -> %.4e%s local_it %d\n",
+                   it + 1, ncg, done, cg_end.rr / cg_end.rr0, use_best ? ", best iterate" : "", dF, lam, res, res_try,
                    accepted ? "" : " (line search failed)", st.local_iters_max);
     if (!accepted) {
       *why = "residual line search failed";
@@ -1063,8 +1072,9 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     res = res_try;
     st.dF_norm = dF;
     st.res_norm = res;
-    // converged when the full Newton correction (not a line-search fraction of it) is small
-    if (lam == 1.0 && dF <= C.opt.newton_tol) return RVE_OK;
+    // converged when the full Newton correction (not a line-search fraction of it) of a
+    // usable linear solve is small
+    if (lam == 1.0 && dF <= C.opt.newton_tol && cg_ok) return RVE_OK;
   }
   *why = "Newton did not converge within max_newton";
   return RVE_ENOCONV;

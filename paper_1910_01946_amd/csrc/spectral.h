@@ -65,6 +65,7 @@ struct XFwdArgs {
   const int32_t* gid;          // XF_CG: grain ids for the frame rotation
   const double* grainR;
   void* x;                     // XF_CG: solution (T), x += alpha p
+  void* xbest;                 // XF_CG: copy of the iterate with the best r.r (T)
   void* r;                     // XF_CG: residual (T), r -= alpha q
   const void* p;               // XF_CG: search direction (T)
   const void* q;               // XF_CG: G(K : p) (T)
@@ -181,6 +182,7 @@ struct PrepArgs {
   const int32_t* gid;
   const double* grainR;
   void* x;
+  void* xbest;                 // copy of the iterate with the best r.r (T)
   void* r;
   const void* p;
   const void* q;

@@ -74,6 +74,11 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
         double ps[9];
         if (a.cg->iter > 0) {
           const double alpha = a.cg->alpha;
+          if (a.cg->it_best == a.cg->iter - 1) {
+            T* XB = reinterpret_cast<T*>(a.xbest);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) XB[c * nv + v] = X[c * nv + v];
+          }
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const int64_t o = c * nv + v;
