@@ -29,14 +29,21 @@ struct AxisPlan {
 __device__ __forceinline__ int padded(int e) { return e + (e >> 3); }
 // line stride for n padded elements
 __host__ __device__ constexpr int padded_len(int n) { return n + (n + 7) / 8; }
+// Start of line l at stride S with one more pad slot after every 4 lines.  At S = 72
+// (64-point lines) the same element of consecutive lines is 144 words apart, 16 banks
+// mod 64, so a transpose that reads or writes one element of 32 consecutive lines per
+// half-wave would hit 4 banks 8 times each; the extra slot every 4 lines spreads those 32
+// lines over distinct banks, and a radix-8 stage (4 lines per half-wave) is unaffected.
+__host__ __device__ constexpr int skewed_line(int l, int S) { return l * S + (l >> 2); }
 
 struct LineLayout {
   int nlines;
   int L1, S1, S0, estride;  // estride 0: contiguous padded lines (element e at padded(e))
+  int skew;                 // 1: one more pad slot after every 4 lines (see skewed_line)
   FastDiv dL1;              // division by L1; the zero value divides by 1
   __device__ __forceinline__ int base(int l) const {
     const int q = fdiv(l, dL1);
-    return q * S1 + (l - q * L1) * S0;
+    return q * S1 + (l - q * L1) * S0 + skew * (l >> 2);
   }
   __device__ __forceinline__ int elem(int e) const { return estride ? e * estride : padded(e); }
 };

@@ -68,11 +68,13 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   }
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
-  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded())
+  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded());
+  // the B lines are also skewed (see skewed_line()): the repack and the spectrum hand-off
+  // touch one element of many consecutive B lines at a time
   const int npair = (ny + 1) / 2, SA = padded_len(nx), SB = padded_len(ny);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* B = A + npair * SA;
-  cplx<T>* twx = B + nxh * SB;
+  cplx<T>* twx = B + skewed_line(nxh, SB);
   cplx<T>* twy = twx + nx;
   const int64_t nv = g.nvox;
   const int64_t base = (int64_t)c * nv + (int64_t)z * ny * nx;
@@ -112,16 +114,16 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
     const cplx<T> Zk = A[p * SA + padded(k)];
     const cplx<T> Zm = A[p * SA + padded(k == 0 ? 0 : nx - k)];
     const T h = (T)0.5;
-    B[k * SB + padded(2 * p)] = cmk(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
-    if (2 * p + 1 < ny) B[k * SB + padded(2 * p + 1)] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
+    B[skewed_line(k, SB) + padded(2 * p)] = cmk(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
+    if (2 * p + 1 < ny) B[skewed_line(k, SB) + padded(2 * p + 1)] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0}, g.ay, twy, (T)-1);
+  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)-1);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   const int64_t sbase = ((int64_t)c * nz + z) * ny * nxh;
   for (int idx = tid; idx < ny * nxh; idx += nthr) {
     const int ky = fdiv(idx, g.fnxh), kx = idx - ky * nxh;
-    spec[sbase + idx] = B[kx * SB + padded(ky)];
+    spec[sbase + idx] = B[skewed_line(kx, SB) + padded(ky)];
   }
 }
 
@@ -132,11 +134,13 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   if (MODE == PI_CG && a.cg->done) return;
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
-  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded())
+  // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded());
+  // the B lines are also skewed (see skewed_line()): the repack and the spectrum hand-off
+  // touch one element of many consecutive B lines at a time
   const int npair = (ny + 1) / 2, SA = padded_len(nx), SB = padded_len(ny);
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* B = A + npair * SA;
-  cplx<T>* twx = B + nxh * SB;
+  cplx<T>* twx = B + skewed_line(nxh, SB);
   cplx<T>* twy = twx + nx;
   const int64_t nv = g.nvox;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -157,18 +161,18 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
       const int idx = b0 + u * nthr;
       if (idx < ny * nxh) {
         const int ky = fdiv(idx, g.fnxh), kx = idx - ky * nxh;
-        B[kx * SB + padded(ky)] = val[u];
+        B[skewed_line(kx, SB) + padded(ky)] = val[u];
       }
     }
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0}, g.ay, twy, (T)1);
+  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)1);
   for (int idx = tid; idx < npair * nx; idx += nthr) {
     const int p = fdiv(idx, g.fnx), k = idx - p * nx;
     const bool hi = k >= nxh;
     const int kk = hi ? nx - k : k;
-    cplx<T> Av = B[kk * SB + padded(2 * p)];
-    cplx<T> Bv = (2 * p + 1 < ny) ? B[kk * SB + padded(2 * p + 1)] : cmk((T)0, (T)0);
+    cplx<T> Av = B[skewed_line(kk, SB) + padded(2 * p)];
+    cplx<T> Bv = (2 * p + 1 < ny) ? B[skewed_line(kk, SB) + padded(2 * p + 1)] : cmk((T)0, (T)0);
     if (hi) {
       Av.y = -Av.y;
       Bv.y = -Bv.y;
@@ -347,7 +351,7 @@ __global__ void k_gnd(int64_t nv, const double* nye, const int32_t* gid, const d
 static size_t plane_lds(const GridPlan& g, bool fp32) {
   const size_t cs = fp32 ? 8 : 16;
   const size_t npair = (g.ny + 1) / 2;
-  return cs * (npair * padded_len(g.nx) + (size_t)g.nxh * padded_len(g.ny) + g.nx + g.ny);
+  return cs * (npair * padded_len(g.nx) + (size_t)skewed_line(g.nxh, padded_len(g.ny)) + g.nx + g.ny);
 }
 
 static int plane_ppt(const GridPlan& g) {

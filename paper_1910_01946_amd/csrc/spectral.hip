@@ -160,7 +160,7 @@ __global__ void k_yfft(GridPlan g, void* spec_, int sign, const CGState* cg) {
     buf[y * typ + j] = (kx0 + j < nxh) ? spec[base + (int64_t)y * nxh + j] : cmk((T)0, (T)0);
   }
   __syncthreads();
-  LineLayout L{ty, ty, 0, 1, typ, make_fastdiv(ty)};
+  LineLayout L{ty, ty, 0, 1, typ, 0, make_fastdiv(ty)};
   fft_lines<T, 16>(buf, L, g.ay, reinterpret_cast<const cplx<T>*>(g.twy), (T)sign);
   for (int idx = tid; idx < ny * ty; idx += nthr) {
     const int y = idx / ty, j = idx - y * ty;
