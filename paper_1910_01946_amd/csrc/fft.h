@@ -22,6 +22,24 @@ struct AxisPlan {
   uint32_t code;  // rad[s] in bits 4s..4s+3 (read by shifts: no indexed access on the device)
 };
 
+// Radix sets.  A kernel compiled for a set carries the stage code of those radices only:
+// the FFT kernels are short chains of code that each wave runs once per launch, so code
+// that a grid never uses still costs instruction-cache misses at every launch.
+enum RadixSet : int { RS_8 = 1, RS_4 = 2, RS_2 = 4, RS_3 = 8, RS_5 = 16, RS_ALL = 31 };
+inline int radix_bits(const AxisPlan& a) {
+  int m = 0;
+  for (int s = 0; s < a.nrad; ++s)
+    m |= a.rad[s] == 8 ? RS_8 : a.rad[s] == 4 ? RS_4 : a.rad[s] == 2 ? RS_2 : a.rad[s] == 3 ? RS_3 : RS_5;
+  return m;
+}
+// the compiled set that covers the radices in need
+inline int radix_set_for(int need) {
+  if ((need & ~RS_8) == 0) return RS_8;
+  if ((need & ~(RS_8 | RS_4)) == 0) return RS_8 | RS_4;
+  if ((need & ~(RS_8 | RS_2)) == 0) return RS_8 | RS_2;
+  return RS_ALL;
+}
+
 // LDS slot of element e of a contiguous line with one pad slot after every 8 elements:
 // radix-8 stages read 8 consecutive elements of each of several lines and write elements
 // 8 apart; with this padding and a line stride of 72 (for 64-point lines) both patterns
@@ -174,19 +192,24 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const LineLayout& L, int
 }
 
 // In-place transform of every line; sign = -1 forward, +1 inverse (unnormalised).
-// PPT: upper bound of (lines * n) / threads, fixed at compile time.
-template <typename T, int PPT>
+// PPT: upper bound of (lines * n) / threads, fixed at compile time.  RS: the radices
+// compiled in; the caller guarantees that it contains every radix of the plan.
+template <typename T, int PPT, int RS = RS_ALL>
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, const LineLayout& L, const AxisPlan& ap, const cplx<T>* __restrict__ tw,
                           T sign) {
   int Ns = 1;
   for (int s = 0; s < ap.nrad; ++s) {
     const int R = (ap.code >> (4 * s)) & 15;
-    switch (R) {
-      case 8: fft_stage<T, 8, (PPT + 7) / 8>(buf, L, ap.n, Ns, tw, sign); break;
-      case 4: fft_stage<T, 4, (PPT + 3) / 4>(buf, L, ap.n, Ns, tw, sign); break;
-      case 2: fft_stage<T, 2, (PPT + 1) / 2>(buf, L, ap.n, Ns, tw, sign); break;
-      case 3: fft_stage<T, 3, (PPT + 2) / 3>(buf, L, ap.n, Ns, tw, sign); break;
-      default: fft_stage<T, 5, (PPT + 4) / 5>(buf, L, ap.n, Ns, tw, sign); break;
+    if constexpr (RS == RS_8) {
+      fft_stage<T, 8, (PPT + 7) / 8>(buf, L, ap.n, Ns, tw, sign);
+    } else {
+      switch (R) {
+        case 8: fft_stage<T, 8, (PPT + 7) / 8>(buf, L, ap.n, Ns, tw, sign); break;
+        case 4: if constexpr ((RS & RS_4) != 0) fft_stage<T, 4, (PPT + 3) / 4>(buf, L, ap.n, Ns, tw, sign); break;
+        case 2: if constexpr ((RS & RS_2) != 0) fft_stage<T, 2, (PPT + 1) / 2>(buf, L, ap.n, Ns, tw, sign); break;
+        case 3: if constexpr ((RS & RS_3) != 0) fft_stage<T, 3, (PPT + 2) / 3>(buf, L, ap.n, Ns, tw, sign); break;
+        default: if constexpr ((RS & RS_5) != 0) fft_stage<T, 5, (PPT + 4) / 5>(buf, L, ap.n, Ns, tw, sign); break;
+      }
     }
     Ns *= R;
   }

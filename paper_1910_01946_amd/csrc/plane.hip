@@ -53,7 +53,7 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* r
 // more threads per plane (fewer points each) shorten the chain.
 constexpr int kPlaneThreads = 512;
 
-template <typename T, int SRC, int PPT>
+template <typename T, int SRC, int PPT, int RS>
 __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, CGState* cg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[8];
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
     }
   }
   __syncthreads();
-  fft_lines<T, PPT>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)-1);
+  fft_lines<T, PPT, RS>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)-1);
   for (int idx = tid; idx < npair * nxh; idx += nthr) {
     const int p = fdiv(idx, g.fnxh), k = idx - p * nxh;
     const cplx<T> Zk = A[p * SA + padded(k)];
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
     if (2 * p + 1 < ny) B[skewed_line(k, SB) + padded(2 * p + 1)] = cmk(h * (Zk.y + Zm.y), h * (Zm.x - Zk.x));
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)-1);
+  fft_lines<T, PPT, RS>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)-1);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   const int64_t sbase = ((int64_t)c * nz + z) * ny * nxh;
   for (int idx = tid; idx < ny * nxh; idx += nthr) {
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   }
 }
 
-template <typename T, int MODE, int PPT>
+template <typename T, int MODE, int PPT, int RS>
 __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneInvArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[8];
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
     }
   }
   __syncthreads();
-  fft_lines<T, PPT>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)1);
+  fft_lines<T, PPT, RS>(B, LineLayout{nxh, 1, SB, 0, 0, 1}, g.ay, twy, (T)1);
   for (int idx = tid; idx < npair * nx; idx += nthr) {
     const int p = fdiv(idx, g.fnx), k = idx - p * nx;
     const bool hi = k >= nxh;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
     A[p * SA + padded(k)] = cmk(Av.x - Bv.y, Av.y + Bv.x);
   }
   __syncthreads();
-  fft_lines<T, PPT>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)1);
+  fft_lines<T, PPT, RS>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)1);
   const int64_t base = (int64_t)c * nv + (int64_t)z * ny * nx;
   double acc = 0.0;
   const double beta = (MODE == PI_CG) ? a.cg->beta : 0.0;
@@ -371,15 +371,29 @@ static hipError_t lds_limit(K kernel, int bytes) {
                              bytes - (int)fa.sharedSizeBytes);
 }
 
+template <typename T, int PPT, int RS>
+static hipError_t plane_limits_rs(int bytes) {
+  hipError_t e = hipSuccess, f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_T, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_F64, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_fwd<T, PF_FPI, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_CG, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_RESID, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_plane_inv<T, PI_OUT64, PPT, RS>, bytes)) != hipSuccess) e = f;
+  return e;
+}
+
+// planes up to PPT 9 (grids to about 96 x 96) have kernels per radix set; larger ones
+// use the general kernels
 template <typename T, int PPT>
 static hipError_t plane_limits_ppt(int bytes) {
   hipError_t e = hipSuccess, f;
-  if ((f = lds_limit(k_plane_fwd<T, PF_T, PPT>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_plane_fwd<T, PF_F64, PPT>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_plane_fwd<T, PF_FPI, PPT>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_plane_inv<T, PI_CG, PPT>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_plane_inv<T, PI_RESID, PPT>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_plane_inv<T, PI_OUT64, PPT>, bytes)) != hipSuccess) e = f;
+  if ((f = plane_limits_rs<T, PPT, RS_ALL>(bytes)) != hipSuccess) e = f;
+  if constexpr (PPT <= 9) {
+    if ((f = plane_limits_rs<T, PPT, RS_8>(bytes)) != hipSuccess) e = f;
+    if ((f = plane_limits_rs<T, PPT, RS_8 | RS_4>(bytes)) != hipSuccess) e = f;
+    if ((f = plane_limits_rs<T, PPT, RS_8 | RS_2>(bytes)) != hipSuccess) e = f;
+  }
   return e;
 }
 
@@ -396,19 +410,32 @@ hipError_t set_plane_lds_limits(int bytes) {
   return e;
 }
 
-template <typename T, int SRC, int PPT>
+// radix set of the plane kernels: the x and y transforms of the grid
+static int plane_radix_set(const GridPlan& g) { return radix_set_for(radix_bits(g.ax) | radix_bits(g.ay)); }
+
+template <typename T, int SRC, int PPT, int RS>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_fwd<T, SRC, PPT>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a, cg);
+  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a, cg);
+}
+
+template <typename T, int SRC, int PPT>
+static void fwd_dispatch_rs(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
+  switch (plane_radix_set(g)) {
+    case RS_8: fwd_launch<T, SRC, PPT, RS_8>(g, a, cg, st); break;
+    case RS_8 | RS_4: fwd_launch<T, SRC, PPT, RS_8 | RS_4>(g, a, cg, st); break;
+    case RS_8 | RS_2: fwd_launch<T, SRC, PPT, RS_8 | RS_2>(g, a, cg, st); break;
+    default: fwd_launch<T, SRC, PPT, RS_ALL>(g, a, cg, st); break;
+  }
 }
 
 template <typename T, int SRC>
 static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const int ppt = plane_ppt(g);
-  if (ppt <= 5) fwd_launch<T, SRC, 5>(g, a, cg, st);
-  else if (ppt <= 9) fwd_launch<T, SRC, 9>(g, a, cg, st);
-  else if (ppt <= 17) fwd_launch<T, SRC, 17>(g, a, cg, st);
-  else fwd_launch<T, SRC, 33>(g, a, cg, st);
+  if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
+  else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
+  else if (ppt <= 17) fwd_launch<T, SRC, 17, RS_ALL>(g, a, cg, st);
+  else fwd_launch<T, SRC, 33, RS_ALL>(g, a, cg, st);
 }
 
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st) {
@@ -423,19 +450,29 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState*
   }
 }
 
-template <typename T, int MODE, int PPT>
+template <typename T, int MODE, int PPT, int RS>
 static void inv_launch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_inv<T, MODE, PPT>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a);
+  launch(k_plane_inv<T, MODE, PPT, RS>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a);
+}
+
+template <typename T, int MODE, int PPT>
+static void inv_dispatch_rs(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
+  switch (plane_radix_set(g)) {
+    case RS_8: inv_launch<T, MODE, PPT, RS_8>(g, a, st); break;
+    case RS_8 | RS_4: inv_launch<T, MODE, PPT, RS_8 | RS_4>(g, a, st); break;
+    case RS_8 | RS_2: inv_launch<T, MODE, PPT, RS_8 | RS_2>(g, a, st); break;
+    default: inv_launch<T, MODE, PPT, RS_ALL>(g, a, st); break;
+  }
 }
 
 template <typename T, int MODE>
 static void inv_dispatch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const int ppt = plane_ppt(g);
-  if (ppt <= 5) inv_launch<T, MODE, 5>(g, a, st);
-  else if (ppt <= 9) inv_launch<T, MODE, 9>(g, a, st);
-  else if (ppt <= 17) inv_launch<T, MODE, 17>(g, a, st);
-  else inv_launch<T, MODE, 33>(g, a, st);
+  if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
+  else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
+  else if (ppt <= 17) inv_launch<T, MODE, 17, RS_ALL>(g, a, st);
+  else inv_launch<T, MODE, 33, RS_ALL>(g, a, st);
 }
 
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st) {

@@ -171,7 +171,7 @@ __global__ void k_yfft(GridPlan g, void* spec_, int sign, const CGState* cg) {
 // ---------------------------------------------------------------------------------------
 // z pass with the pointwise operator
 // ---------------------------------------------------------------------------------------
-template <typename T, int OP>
+template <typename T, int OP, int RS>
 __global__ void k_mid(GridPlan g, MidArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -217,7 +217,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   }
   __syncthreads();
   LineLayout L{9 * tz, 1, SZ, 0, 0};
-  fft_lines<T, 9>(buf, L, g.az, twz, (T)-1);
+  fft_lines<T, 9, RS>(buf, L, g.az, twz, (T)-1);
   const cplx<double>* Ex = reinterpret_cast<const cplx<double>*>(g.Ex);
   const cplx<double>* Ey = reinterpret_cast<const cplx<double>*>(g.Ey);
   const cplx<double>* Ez = reinterpret_cast<const cplx<double>*>(g.Ez);
@@ -281,7 +281,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     }
   }
   __syncthreads();
-  fft_lines<T, 9>(buf, L, g.az, twz, (T)1);
+  fft_lines<T, 9, RS>(buf, L, g.az, twz, (T)1);
   for (int idx = tid; idx < nload; idx += nthr) {
     const int t = fdiv(idx, g.ftz), j = idx - t * tz;
     const int c = fdiv(t, g.fnz), zz = t - c * nz;
@@ -504,6 +504,14 @@ static hipError_t lds_limit(K kernel, int bytes) {
                              bytes - (int)fa.sharedSizeBytes);
 }
 
+template <typename T, int RS>
+static hipError_t mid_limits(int bytes) {
+  hipError_t e = hipSuccess, f;
+  if ((f = lds_limit(k_mid<T, MID_GREEN, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_mid<T, MID_CURL, RS>, bytes)) != hipSuccess) e = f;
+  return e;
+}
+
 template <typename T>
 static hipError_t spectral_limits(int bytes) {
   hipError_t e = hipSuccess, f;
@@ -511,8 +519,10 @@ static hipError_t spectral_limits(int bytes) {
   if ((f = lds_limit(k_xfwd<T, XF_CG>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_xfwd<T, XF_FP_MINUS_I>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_yfft<T>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_mid<T, MID_GREEN>, bytes)) != hipSuccess) e = f;
-  if ((f = lds_limit(k_mid<T, MID_CURL>, bytes)) != hipSuccess) e = f;
+  if ((f = mid_limits<T, RS_ALL>(bytes)) != hipSuccess) e = f;
+  if ((f = mid_limits<T, RS_8>(bytes)) != hipSuccess) e = f;
+  if ((f = mid_limits<T, RS_8 | RS_4>(bytes)) != hipSuccess) e = f;
+  if ((f = mid_limits<T, RS_8 | RS_2>(bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_xinv<T, XI_RESID>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_xinv<T, XI_CG>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_xinv<T, XI_NYE>, bytes)) != hipSuccess) e = f;
@@ -566,21 +576,30 @@ int mid_blocks(const GridPlan& g) {
   return 8 * ((nblk + 7) / 8);
 }
 
+template <typename T, int OP, int RS>
+static void mid_launch(const GridPlan& g, const MidArgs& a, hipStream_t st) {
+  const size_t sh = ((size_t)9 * g.tz * padded_len(g.nz) + g.nz) * sizeof(cplx<T>);
+  launch(k_mid<T, OP, RS>, dim3(mid_blocks(g)), dim3(256), (uint32_t)sh, st, g, a);
+}
+
+// radix set of the z transform
+template <typename T, int OP>
+static void mid_dispatch(const GridPlan& g, const MidArgs& a, hipStream_t st) {
+  switch (radix_set_for(radix_bits(g.az))) {
+    case RS_8: mid_launch<T, OP, RS_8>(g, a, st); break;
+    case RS_8 | RS_4: mid_launch<T, OP, RS_8 | RS_4>(g, a, st); break;
+    case RS_8 | RS_2: mid_launch<T, OP, RS_8 | RS_2>(g, a, st); break;
+    default: mid_launch<T, OP, RS_ALL>(g, a, st); break;
+  }
+}
+
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) {
-  const dim3 grid(mid_blocks(g));
-  const size_t sh = ((size_t)9 * g.tz * padded_len(g.nz) + g.nz) * (fp32 ? 8 : 16);
   if (fp32) {
-    if (a.op == MID_GREEN) {
-      launch(k_mid<float, MID_GREEN>, grid, dim3(256), (uint32_t)sh, st, g, a);
-    } else {
-      launch(k_mid<float, MID_CURL>, grid, dim3(256), (uint32_t)sh, st, g, a);
-    }
+    if (a.op == MID_GREEN) mid_dispatch<float, MID_GREEN>(g, a, st);
+    else mid_dispatch<float, MID_CURL>(g, a, st);
   } else {
-    if (a.op == MID_GREEN) {
-      launch(k_mid<double, MID_GREEN>, grid, dim3(256), (uint32_t)sh, st, g, a);
-    } else {
-      launch(k_mid<double, MID_CURL>, grid, dim3(256), (uint32_t)sh, st, g, a);
-    }
+    if (a.op == MID_GREEN) mid_dispatch<double, MID_GREEN>(g, a, st);
+    else mid_dispatch<double, MID_CURL>(g, a, st);
   }
 }
 
