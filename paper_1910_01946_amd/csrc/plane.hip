@@ -383,8 +383,8 @@ static hipError_t plane_limits_rs(int bytes) {
   return e;
 }
 
-// planes up to PPT 9 (grids to about 96 x 96) have kernels per radix set; larger ones
-// use the general kernels
+// planes up to PPT 9 (grids to about 96 x 96) have kernels per radix set, PPT 17 (to
+// 128 x 128) for radices 8 and 2 (128 = 8 8 2); the others use the general kernels
 template <typename T, int PPT>
 static hipError_t plane_limits_ppt(int bytes) {
   hipError_t e = hipSuccess, f;
@@ -392,6 +392,8 @@ static hipError_t plane_limits_ppt(int bytes) {
   if constexpr (PPT <= 9) {
     if ((f = plane_limits_rs<T, PPT, RS_8>(bytes)) != hipSuccess) e = f;
     if ((f = plane_limits_rs<T, PPT, RS_8 | RS_4>(bytes)) != hipSuccess) e = f;
+  }
+  if constexpr (PPT <= 17) {
     if ((f = plane_limits_rs<T, PPT, RS_8 | RS_2>(bytes)) != hipSuccess) e = f;
   }
   return e;
@@ -434,6 +436,7 @@ static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hip
   const int ppt = plane_ppt(g);
   if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
   else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
+  else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) fwd_launch<T, SRC, 17, RS_8 | RS_2>(g, a, cg, st);
   else if (ppt <= 17) fwd_launch<T, SRC, 17, RS_ALL>(g, a, cg, st);
   else fwd_launch<T, SRC, 33, RS_ALL>(g, a, cg, st);
 }
@@ -471,6 +474,7 @@ static void inv_dispatch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t s
   const int ppt = plane_ppt(g);
   if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
   else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
+  else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) inv_launch<T, MODE, 17, RS_8 | RS_2>(g, a, st);
   else if (ppt <= 17) inv_launch<T, MODE, 17, RS_ALL>(g, a, st);
   else inv_launch<T, MODE, 33, RS_ALL>(g, a, st);
 }
