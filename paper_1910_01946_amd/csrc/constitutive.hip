@@ -33,6 +33,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 
 namespace rve {
@@ -440,7 +442,11 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
       for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];   // + e_k (x) H_l.
       const int col = 3 * kk + ll;
 #pragma unroll
-      for (int r = 0; r < 9; ++r) Kout[tangent_index<KT>(r * 9 + col, v, nv, args.k_grouped)] = (KT)dP[r];
+      for (int r = 0; r < 9; ++r) {
+        const int64_t ki = tangent_index<KT>(r * 9 + col, v, nv, args.k_grouped);
+        if constexpr (sizeof(KT) == 2) Kout[ki] = __float2half((float)(dP[r] * args.k_inv_scale));
+        else Kout[ki] = (KT)dP[r];
+      }
     }
   }
 }
@@ -514,7 +520,7 @@ __global__ void k_rotate_tangent(int64_t nv, const int32_t* gid, const double* g
   }
 }
 
-void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st, LaunchTimer* timer) {
+void launch_constitutive(const ConstArgs& a, int ktype, hipStream_t st, LaunchTimer* timer) {
   const int bs = 64;
   const int64_t nb = (a.nvox + bs - 1) / bs;
   const int nb_slow = (int)std::min<int64_t>(nb, 4096);
@@ -529,7 +535,8 @@ void launch_constitutive(const ConstArgs& a, bool fp32, hipStream_t st, LaunchTi
   }
   {
     TimedLaunch t(timer, KF_STRESS_TANGENT, a.nvox, st);
-    if (fp32) launch(k_stress_tangent<float>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
+    if (ktype == KT_F16) launch(k_stress_tangent<__half>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
+    else if (ktype == KT_F32) launch(k_stress_tangent<float>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
     else launch(k_stress_tangent<double>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
   }
 }

@@ -44,7 +44,13 @@ struct ConstArgs {
   double lam_base;               // dg (and dgdF) were computed at F + lam_base * dF
   int32_t predict;               // 1: the first pass starts from dg + (lam - lam_base) dgdF : dF_c
   int32_t k_grouped;             // K layout: 0 entry-major (e * nvox + v), 1 grouped (see tangent_index)
+  double k_inv_scale;            // FP16 K only: entries are stored as dP/dF times this factor
 };
+
+// Storage type of the tangent copy: FP64, FP32, or FP16 pairs scaled by 1/C11 (entries
+// of order one; FP16 rounding, 2^-11 relative, perturbs only the Jacobian that the linear
+// solve inverts, not the residual, so it changes the Newton path and not the solution).
+enum TangentType : int { KT_F64 = 0, KT_F32 = 1, KT_F16 = 2 };
 
 // Layout of the tangent copy used by the conjugate-gradient kernels.  FP64: the 81
 // entries of a voxel in 16-byte groups of W = 2 consecutive entries, group-major over
@@ -54,7 +60,7 @@ struct ConstArgs {
 // costs more occupancy than the wider loads gain.
 template <typename KT>
 struct TangentGroups {
-  static constexpr int W = sizeof(KT) == 8 ? 2 : 1;
+  static constexpr int W = sizeof(KT) == 4 ? 1 : 2;
   static constexpr int G = (81 + W - 1) / W;  // groups per voxel (last one padded)
 };
 template <typename KT>
@@ -74,8 +80,8 @@ struct CommitArgs {
   const double* rho_gnd;
 };
 
-// fp32_tangent: store K in FP32 (else FP64).  dF, when given, is an FP64 field.
-void launch_constitutive(const ConstArgs& a, bool fp32_tangent, hipStream_t st, LaunchTimer* timer = nullptr);
+// ktype: storage type of K (TangentType).  dF, when given, is an FP64 field.
+void launch_constitutive(const ConstArgs& a, int ktype, hipStream_t st, LaunchTimer* timer = nullptr);
 void launch_commit(const CommitArgs& a, hipStream_t st);
 void launch_rotate_tangent(int64_t nv, const int32_t* gid, const double* grainR, const double* Kc, double* Ks,
                            hipStream_t st);

@@ -15,6 +15,8 @@
 // which touches the spectrum four times per iteration.
 #include "spectral.h"
 
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -244,8 +246,8 @@ __device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
 
 // x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame); the
 // iterate is copied to xbest first when the previous iteration set a new best r.r.
-template <typename T>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
+template <typename T, int K16>
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
   if (cg->done) return;
@@ -287,7 +289,25 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 6 : 4) k_cg_prep(int64_t
 #pragma unroll
     for (int i = 0; i < 9; ++i) Rg[i] = a.grainR[9 * gi + i];
     to_crystal(Rg, rs, rc);
-    if constexpr (KG::W == 1) {
+    if constexpr (K16 != 0) {
+      // FP16 pairs (41 4-byte loads per voxel), scaled: the tangent stream dominates the
+      // kernel's bytes, and this halves it
+      const __half2* K2 = reinterpret_cast<const __half2*>(a.K);
+      float kv[82];
+#pragma unroll
+      for (int gq = 0; gq < 41; ++gq) {
+        const float2 f = __half22float2(K2[(int64_t)gq * nv + v]);
+        kv[2 * gq] = f.x;
+        kv[2 * gq + 1] = f.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) s += (double)kv[i * 9 + j] * rc[j];
+        yc[i] = s * a.k_scale;
+      }
+    } else if constexpr (KG::W == 1) {
       // FP32: entry-major, loads interleaved with the products (keeps occupancy)
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -498,10 +518,11 @@ int prep_blocks(const GridPlan& g) {
   return (int)std::min<int64_t>(nb, 1024);
 }
 
-void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st) {
+void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, const PrepArgs& a, hipStream_t st) {
   const int nb = prep_blocks(g);
-  if (fp32) launch(k_cg_prep<float>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
-  else launch(k_cg_prep<double>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  if (fp32 && k16) launch(k_cg_prep<float, 1>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else if (fp32) launch(k_cg_prep<float, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else launch(k_cg_prep<double, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
 }
 
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,

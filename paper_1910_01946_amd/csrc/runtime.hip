@@ -343,12 +343,19 @@ struct Work {
   Plan plan;
   DevBuf K, xa, xb, xbest, r, p, q, y, spec;
   bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
+  bool k16 = false;    // FP32 work set with the plane path: tangent copy as scaled FP16 pairs
 };
 
 // RVE_PLANE=0 in the environment selects the three-pass (x, y, z) spectral kernels even
 // where the plane kernels fit (both are kept and tested).
 static bool plane_enabled() {
   const char* e = std::getenv("RVE_PLANE");
+  return !(e && e[0] == '0');
+}
+
+// RVE_TANGENT16=0 keeps the mixed form's tangent copy in FP32.
+static bool tangent16_enabled() {
+  const char* e = std::getenv("RVE_TANGENT16");
   return !(e && e[0] == '0');
 }
 
@@ -429,9 +436,11 @@ struct EventTimer final : LaunchTimer {
 // Algorithmic bytes of one launch (compulsory HBM traffic: every input read once, every
 // output written once).  T = spectral precision, nv voxels, ns = nxh ny nz spectral points.
 static int64_t bytes_mid(const GridPlan& g, bool fp32) { return 2 * 9 * 2 * (fp32 ? 4 : 8) * g.nspec; }
-static int64_t bytes_cg_prep(const GridPlan& g, bool fp32, bool first) {
-  // x, p, r, q, K read and x, r, y written (first iteration: r, K read and y written)
-  return (first ? 99 : 144) * (fp32 ? 4 : 8) * g.nvox + 4 * g.nvox;
+static int64_t bytes_cg_prep(const GridPlan& g, bool fp32, bool k16, bool first) {
+  // x, p, r, q, K read and x, r, y written (first iteration: r, K read and y written);
+  // K: 81 entries, or 41 pairs of FP16
+  const int t = fp32 ? 4 : 8;
+  return ((first ? 18 : 63) * t + (k16 ? 41 * 4 : 81 * t) + 4) * g.nvox;
 }
 static int64_t bytes_plane_fwd_cg(const GridPlan& g, bool fp32) {
   const int t = fp32 ? 4 : 8;
@@ -522,6 +531,8 @@ static Work& work(RVE& R, bool fp32) {
     w.ready = true;
   }
   w.plane = plane_enabled() && plane_fits(w.plan.g, fp32);
+  // (K is allocated at the FP32 size, which holds the FP16 pairs too)
+  w.k16 = fp32 && w.plane && tangent16_enabled();
   return w;
 }
 
@@ -616,13 +627,14 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.P = R.P_work.as<double>();
   a.K = tangent ? w.K.p : nullptr;
   a.k_grouped = 1;
+  a.k_inv_scale = w.k16 ? 1.0 / R.mat.C11 : 1.0;
   a.dt = dt;
   a.stats = R.blk.as<int32_t>();
   a.work = R.blk.as<int32_t>() + 4;
   a.dgdF = tangent ? R.dgdF.as<float>() : nullptr;
   a.predict = (predict && dF && prediction_enabled()) ? 1 : 0;
   a.lam_base = lam_base;
-  launch_constitutive(a, w.fp32, R.stream, R.tm());
+  launch_constitutive(a, !w.fp32 ? KT_F64 : (w.k16 ? KT_F16 : KT_F32), R.stream, R.tm());
   check_launch("constitutive");
   int32_t st4[4];
   HIPCHECK(hipMemcpyAsync(st4, R.blk.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, R.stream));
@@ -842,6 +854,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pr.y = w.y.p;
   pr.cg = cg;
   pr.partial = part;
+  pr.k_scale = w.k16 ? R.mat.C11 : 1.0;
   PlaneArgs pa{PF_T, w.y.p, w.spec.p};
   pa.rr_partial = part;
   pa.n_rr = prep_blocks(g);
@@ -863,8 +876,8 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
       R.timer.tag = issued;
       pa.it = issued;
       {
-        TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, issued == 0), R.stream);
-        launch_cg_prep(g, w.fp32, pr, R.stream);
+        TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, w.k16, issued == 0), R.stream);
+        launch_cg_prep(g, w.fp32, w.k16, pr, R.stream);
       }
       {
         TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_cg(g, w.fp32), R.stream);
@@ -1520,7 +1533,7 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
     a.iters = iters;
     a.stats = cnt.as<int32_t>();
     a.work = cnt.as<int32_t>() + 4;
-    launch_constitutive(a, false, st);
+    launch_constitutive(a, KT_F64, st);
     check_launch("constitutive");
     if (K) {
       launch_rotate_tangent(nvox, gid, dR.as<double>(), Kc.as<double>(), K, st);

@@ -189,6 +189,7 @@ struct PrepArgs {
   void* y;                     // out: K : r (T)
   CGState* cg;
   double* partial;             // per-block r.r
+  double k_scale;              // FP16 K: y = k_scale (K16 : r)
 };
 
 bool plane_fits(const GridPlan& g, bool fp32);
@@ -200,7 +201,7 @@ int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
-void launch_cg_prep(const GridPlan& g, bool fp32, const PrepArgs& a, hipStream_t st);
+void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, const PrepArgs& a, hipStream_t st);
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,
                 double* rho_gnd, hipStream_t st);
 
