@@ -104,10 +104,16 @@ print(json.dumps({"vi": st["voxel_iterations"], "sec": dt, "conv": st["converged
 
 
 def source_digest(files):
+    """Digest of the code of the given sources, comments and blank lines left out (a change
+    of wording does not invalidate stored counter readings; a change of code does)."""
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1910_01946_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1910_01946_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode("utf-8"))
     return h.hexdigest()[:16]
 
 

@@ -52,12 +52,11 @@ struct ConstArgs {
 // solve inverts, not the residual, so it changes the Newton path and not the solution).
 enum TangentType : int { KT_F64 = 0, KT_F32 = 1, KT_F16 = 2 };
 
-// Layout of the tangent copy used by the conjugate-gradient kernels.  FP64: the 81
-// entries of a voxel in 16-byte groups of W = 2 consecutive entries, group-major over
-// voxels, so that one lane reads two entries with one vector load while a wavefront still
-// reads contiguous memory (fewer memory instructions in flight per voxel).  FP32: entry-
-// major (W = 1); 16-byte groups there need the whole tangent in registers at once, which
-// costs more occupancy than the wider loads gain.
+// Layout of the tangent copy used by the conjugate-gradient kernels.  FP64 and FP16: the
+// 81 entries of a voxel in groups of W = 2 consecutive entries (16 and 4 bytes), group-major
+// over voxels, so that one lane reads two entries with one vector load while a wavefront
+// still reads contiguous memory (fewer memory instructions in flight per voxel).  FP32:
+// entry-major (W = 1); wider groups there cost more registers and occupancy than they gain.
 template <typename KT>
 struct TangentGroups {
   static constexpr int W = sizeof(KT) == 4 ? 1 : 2;

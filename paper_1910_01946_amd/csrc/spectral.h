@@ -178,7 +178,7 @@ struct PlaneInvArgs {
 };
 
 struct PrepArgs {
-  const void* K;               // crystal-frame tangent (T)
+  const void* K;               // crystal-frame tangent (T, or FP16 pairs: see launch_cg_prep)
   const int32_t* gid;
   const double* grainR;
   void* x;
@@ -201,6 +201,8 @@ int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
+// k16: the tangent copy is FP16 pairs scaled by 1/k_scale (grouped layout of
+// TangentGroups<__half>); otherwise it is in the CG precision
 void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, const PrepArgs& a, hipStream_t st);
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,
                 double* rho_gnd, hipStream_t st);
