@@ -135,6 +135,22 @@ int32_t rve_nye_gnd(rve_handle h, int32_t rve, double* nye, double* rho_gnd);
  * sigma may be NULL. */
 int32_t rve_macro_stress(rve_handle h, int32_t rve, double* P_avg, double* F_avg, double* sigma);
 
+/* Adjoint of the linearised equilibrium of eq. 18 at the last converged increment: solves
+ * G(K^T : lambda) = G(g) for lambda in the range of G, where K is the consistent tangent
+ * dP/dF of that increment's last constitutive evaluation, (K^T)_(ij)(kl) = K_(kl)(ij), and G
+ * the projection of eq. 17 with the zero-frequency rule of mask (as in rve_project).  This
+ * is the first step of an increment's reverse pass (lambda is the multiplier of the
+ * equilibrium constraint for a loss with dL/dF = g).  Same conjugate-gradient kernels as the
+ * forward solve, with the tangent read transposed; the handle's cg_tol and max_cg apply.
+ * g, lambda: device FP64, 9 x nvox (component-major, as the fields of rve_get_field);
+ * lambda may alias g.  mask: host, 9 entries.  cg_iters (host, may be NULL) receives the
+ * CG iteration count.  Errors: RVE_EINVAL for a bad argument, a handle that is not
+ * RVE_FP64, an RVE with no increment taken yet, or a grid whose planes do not fit in LDS;
+ * RVE_ENOCONV when CG ends without reaching cg_tol (breakdown, divergence, iteration cap;
+ * lambda then holds the current iterate). */
+int32_t rve_adjoint_solve(rve_handle h, int32_t rve, const uint8_t* mask, const double* g, double* lambda,
+                          int32_t* cg_iters);
+
 /* Copy a committed field to a host buffer: which = 0 F (9), 1 P (9), 2 Fp (9),
  * 3 rho_SSD (12), 4 rho_GND (12), 5 Nye tensor (9), 6 slip increments of the last
  * increment (12).  Component-major, nvox per component. */

@@ -60,6 +60,21 @@ def conjugate_gradient(apply, b, tol, maxit):
     return x, it
 
 
+def adjoint_operator(project, K, mask):
+    """y -> G(K^T : y), (K^T)_(ij)(kl) = K_(kl)(ij): the transpose of the operator x -> G(K : x)
+    of eq. 18 under the voxel-sum inner product (G is an orthogonal projection, so it is its
+    own transpose).  project(A, mask) applies G to a (V, 3, 3) field; K is (V, 3, 3, 3, 3)."""
+    def apply(y):
+        return project(np.einsum("vklij,vkl->vij", K, y), mask)
+    return apply
+
+
+def adjoint_solve(project, K, g, mask, tol, maxit):
+    """Multiplier of the linearised equilibrium for a loss with dL/dF = g: G(K^T : lam) =
+    G(g), by the same conjugate gradients as the forward solve of eq. 18."""
+    return conjugate_gradient(adjoint_operator(project, K, mask), project(g, mask), tol, maxit)
+
+
 class RVESolver:
     """State and increment loop of one RVE (synth.RVE)."""
 

@@ -123,6 +123,15 @@ class Homogenizer:
         check(lib().rve_timing_read(self.h, _lib.KERNEL_FAMILIES[family], C.byref(n), C.byref(t), C.byref(u)))
         return n.value, t.value, u.value
 
+    def adjoint_solve(self, g, mask, lam, i=0):
+        """Solve G(K^T : lam) = G(g) at the last increment of RVE i (rve_adjoint_solve).
+        g, lam: device float64 tensors of 9 x nvox; returns the CG iteration count."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(9))
+        n = C.c_int32(0)
+        check(lib().rve_adjoint_solve(self.h, i, m.ctypes.data_as(C.POINTER(C.c_uint8)), _ptr(g), _ptr(lam),
+                                      C.byref(n)))
+        return n.value
+
     def save_state(self):
         nb = lib().rve_state_bytes(self.h)
         buf = np.zeros(nb, dtype=np.uint8)

@@ -100,6 +100,8 @@ def lib():
     L.rve_timing_start.restype = C.c_int32
     L.rve_timing_read.argtypes = [vp, C.c_int32, P(C.c_int64), dp, dp]
     L.rve_timing_read.restype = C.c_int32
+    L.rve_adjoint_solve.argtypes = [vp, C.c_int32, P(C.c_uint8), vp, vp, P(C.c_int32)]
+    L.rve_adjoint_solve.restype = C.c_int32
     _lib = L
     return L
 
@@ -108,7 +110,7 @@ def lib():
 EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress", "rve_get_field",
            "rve_state_bytes", "rve_save_state", "rve_load_state", "rve_destroy", "rve_last_error",
            "rve_constitutive_batch", "rve_project", "rve_spectral_curl", "rve_timing_start",
-           "rve_timing_read"]
+           "rve_timing_read", "rve_adjoint_solve"]
 
 # kernel families of rve_timing_start / rve_timing_read
 KERNEL_FAMILIES = {"slip_fast": 0, "slip_slow": 1, "stress_tangent": 2, "cg_prep": 3, "plane_fwd": 4, "mid": 5,

@@ -244,9 +244,10 @@ __device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
   }
 }
 
-// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame); the
-// iterate is copied to xbest first when the previous iteration set a new best r.r.
-template <typename T, int K16>
+// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame; with TR,
+// y = K^T : r, (K^T)_(ij)(kl) = K_(kl)(ij), for the adjoint system); the iterate is copied to
+// xbest first when the previous iteration set a new best r.r.
+template <typename T, int K16, int TR>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
       for (int i = 0; i < 9; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) s += (double)kv[i * 9 + j] * rc[j];
+        for (int j = 0; j < 9; ++j) s += (double)kv[TR ? j * 9 + i : i * 9 + j] * rc[j];
         yc[i] = s * a.k_scale;
       }
     } else if constexpr (KG::W == 1) {
@@ -313,7 +314,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
       for (int i = 0; i < 9; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) s += (double)K[(int64_t)(i * 9 + j) * nv + v] * rc[j];
+        for (int j = 0; j < 9; ++j) s += (double)K[(int64_t)(TR ? j * 9 + i : i * 9 + j) * nv + v] * rc[j];
         yc[i] = s;
       }
     } else {
@@ -329,7 +330,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
       for (int i = 0; i < 9; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) s += (double)kv[i * 9 + j] * rc[j];
+        for (int j = 0; j < 9; ++j) s += (double)kv[TR ? j * 9 + i : i * 9 + j] * rc[j];
         yc[i] = s;
       }
     }
@@ -518,11 +519,12 @@ int prep_blocks(const GridPlan& g) {
   return (int)std::min<int64_t>(nb, 1024);
 }
 
-void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, const PrepArgs& a, hipStream_t st) {
+void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, bool transpose, const PrepArgs& a, hipStream_t st) {
   const int nb = prep_blocks(g);
-  if (fp32 && k16) launch(k_cg_prep<float, 1>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
-  else if (fp32) launch(k_cg_prep<float, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
-  else launch(k_cg_prep<double, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  if (transpose) launch(k_cg_prep<double, 0, 1>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else if (fp32 && k16) launch(k_cg_prep<float, 1, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else if (fp32) launch(k_cg_prep<float, 0, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
+  else launch(k_cg_prep<double, 0, 0>, dim3(nb), dim3(256), 0u, st, g.nvox, a);
 }
 
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,

@@ -344,6 +344,7 @@ struct Work {
   DevBuf K, xa, xb, xbest, r, p, q, y, spec;
   bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
   bool k16 = false;    // FP32 work set with the plane path: tangent copy as scaled FP16 pairs
+  bool k_ready = false;  // K holds the tangent of the last constitutive evaluation with tangent
 };
 
 // RVE_PLANE=0 in the environment selects the three-pass (x, y, z) spectral kernels even
@@ -635,6 +636,7 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.predict = (predict && dF && prediction_enabled()) ? 1 : 0;
   a.lam_base = lam_base;
   launch_constitutive(a, !w.fp32 ? KT_F64 : (w.k16 ? KT_F16 : KT_F32), R.stream, R.tm());
+  if (tangent) w.k_ready = true;
   check_launch("constitutive");
   int32_t st4[4];
   HIPCHECK(hipMemcpyAsync(st4, R.blk.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, R.stream));
@@ -794,7 +796,8 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
 }
 
 // conjugate gradients on G(K : x) = r (x, r, p set by run_residual); returns iterations
-static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int& done_code) {
+static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int& done_code,
+                  bool transpose = false) {
   const GridPlan& g = w.plan.g;
   CGState* cg = R.cg.as<CGState>();
   double* part = R.partial.as<double>();
@@ -877,7 +880,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
       pa.it = issued;
       {
         TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, w.k16, issued == 0), R.stream);
-        launch_cg_prep(g, w.fp32, w.k16, pr, R.stream);
+        launch_cg_prep(g, w.fp32, w.k16, transpose, pr, R.stream);
       }
       {
         TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_cg(g, w.fp32), R.stream);
@@ -1427,6 +1430,32 @@ int32_t rve_nye_gnd(rve_handle h, int32_t rve, double* nye, double* rho_gnd) {
   if (nye) rc = rve_get_field(h, rve, 5, nye);
   if (rc == RVE_OK && rho_gnd) rc = rve_get_field(h, rve, 4, rho_gnd);
   return rc;
+}
+
+int32_t rve_adjoint_solve(rve_handle h, int32_t rve, const uint8_t* mask, const double* g, double* lambda,
+                          int32_t* cg_iters) {
+  return guarded([&]() -> int32_t {
+    if (!h || rve < 0 || rve >= (int32_t)h->rves.size() || !mask || !g || !lambda)
+      throw Error(RVE_EINVAL, "bad argument");
+    if (h->fp32) throw Error(RVE_EINVAL, "the adjoint solve needs an RVE_FP64 handle");
+    HIPCHECK(hipSetDevice(h->device));
+    RVE& R = *h->rves[rve];
+    Work& w = work(R, false);
+    if (!w.k_ready) throw Error(RVE_EINVAL, "no tangent yet: take an increment first");
+    if (!w.plane) throw Error(RVE_EINVAL, "the adjoint solve needs the plane kernels");
+    double keep[9];
+    for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+    // r = -G(g), x = 0; CG on G(K^T : x) = r gives x = -lambda
+    void* x = w.xa.p;
+    run_residual(*h, R, w, g, keep, nullptr, x);
+    int done = 0;
+    const int n = run_cg(*h, R, w, x, keep, done, true);
+    launch_negate(static_cast<const double*>(x), lambda, 9 * R.nvox, R.stream);
+    check_launch("adjoint");
+    HIPCHECK(hipStreamSynchronize(R.stream));
+    if (cg_iters) *cg_iters = n;
+    return (done == 1 || done == 5) ? RVE_OK : RVE_ENOCONV;
+  });
 }
 
 // state: per RVE F, F_prev, Fp (9 each), rho_ssd, rho_gnd, dg (12 each), nye, P (9 each),

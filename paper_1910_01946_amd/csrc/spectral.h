@@ -149,6 +149,7 @@ int launch_colsum(const double* f, int ncomp, int64_t nvox, double* partial, hip
 int launch_sumsq(const void* f, bool fp32, int64_t n, double* partial, hipStream_t st);
 // out[i] = (double)in[i], i < n
 void launch_widen(const float* in, double* out, int64_t n, hipStream_t st);
+void launch_negate(const double* in, double* out, int64_t n, hipStream_t st);
 
 // ---- plane path (x and y transforms of one component plane in LDS) ----------------
 enum PlaneSrc { PF_T = 0, PF_F64 = 1, PF_FPI = 2 };
@@ -202,8 +203,9 @@ int prep_blocks(const GridPlan& g);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
 // k16: the tangent copy is FP16 pairs scaled by 1/k_scale (grouped layout of
-// TangentGroups<__half>); otherwise it is in the CG precision
-void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, const PrepArgs& a, hipStream_t st);
+// TangentGroups<__half>); otherwise it is in the CG precision.  transpose: apply K^T (FP64
+// only, for the adjoint system)
+void launch_cg_prep(const GridPlan& g, bool fp32, bool k16, bool transpose, const PrepArgs& a, hipStream_t st);
 void launch_gnd(int64_t nv, const double* nye, const int32_t* gid, const double* grainR, const MatDev* mat,
                 double* rho_gnd, hipStream_t st);
 

@@ -645,6 +645,16 @@ __global__ void k_widen(const float* in, double* out, int64_t n) {
     out[i] = (double)in[i];
 }
 
+__global__ void k_negate(const double* in, double* out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = -in[i];
+}
+
+void launch_negate(const double* in, double* out, int64_t n, hipStream_t st) {
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_negate, dim3((unsigned)nb), dim3(256), 0, st, in, out, n);
+}
+
 void launch_widen(const float* in, double* out, int64_t n, hipStream_t st) {
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_widen, dim3((unsigned)nb), dim3(256), 0, st, in, out, n);

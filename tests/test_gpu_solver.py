@@ -3,8 +3,8 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import nye, solver
-from tests.gpu_util import from_abi, rel_norm
+from oracle import constitutive, nye, solver
+from tests.gpu_util import cuda, from_abi, rel_norm, to_abi
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +129,49 @@ def test_ragged_grid_fp64_matches_oracle(lib):
         # converged to the FP64 rounding floor of the residual, as in the 8^3 Cu case
         assert np.max(np.abs(Pg - Po)) <= 1e-9 * np.abs(Po).max()
     _check_gnd_fields(h, o, rve)
+
+
+def test_adjoint_solve_matches_oracle_transposed_cg(lib):
+    """rve_adjoint_solve after three increments of the 64-grain SGCP workload at 6^3 (FP64):
+    lam from G(K^T : lam) = G(g) against the oracle's conjugate gradients with its own tangent
+    (central differences) at the same converged state (measured 2e-7 apart; bar 1e-5).  The
+    untransposed system's solution differs by more than 2e-3, which the test checks, so a plain
+    K : lam fails it."""
+    rves, path = synth.workload("cu64", n_override=6, n_inc_override=50)
+    rve = rves[0]
+    h = lib.Homogenizer([rve], precision=lib.RVE_FP64, newton_tol=1e-13, cg_tol=1e-12, max_cg=4000)
+    o = solver.RVESolver(rve, newton_tol=1e-13, cg_tol=1e-12)
+    for k in range(1, 4):
+        if k == 3:
+            Fp_n, rs_n, rg_n = o.Fp.copy(), o.rho_ssd.copy(), o.rho_gnd.copy()
+        assert o.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)["converged"]
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+    K = constitutive.tangent_fd(o.model, o.gid, o.F, Fp_n, rs_n, rg_n, path.dt, o.dg)
+    g = np.random.default_rng(5).standard_normal((rve.n_vox, 3, 3))
+    lam_o, _ = solver.adjoint_solve(o.project, K, g, path.mask, 1e-12, 4000)
+    lam_k, _ = solver.conjugate_gradient(lambda y: o.project(np.einsum("vijkl,vkl->vij", K, y), path.mask),
+                                         o.project(g, path.mask), 1e-12, 4000)
+    gt = cuda(to_abi(g))
+    lt = gt.clone()
+    print("adjoint solve 6^3 after 3 increments", flush=True)
+    it = h.adjoint_solve(gt, path.mask, lt)
+    lam_g = from_abi(lt.cpu().numpy())
+    err, sep = rel_norm(lam_g, lam_o), rel_norm(lam_k, lam_o)
+    print("adjoint: cg", it, "gpu vs oracle", err, "K vs K^T solutions", sep, flush=True)
+    assert sep > 2e-3
+    assert err < 1e-5
+
+
+def test_adjoint_solve_rejects_a_mixed_handle_and_an_unstepped_rve(lib):
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    g = cuda(np.zeros((9, rves[0].n_vox)))
+    h = lib.Homogenizer(rves, precision=lib.RVE_FP64)
+    with pytest.raises(lib.RVEError):
+        h.adjoint_solve(g, path.mask, g.clone())          # no increment taken yet
+    hm = lib.Homogenizer(rves, precision=lib.RVE_MIXED)
+    hm.step(path.F_bar[1], path.mask, path.P_bar[1], path.dt)
+    with pytest.raises(lib.RVEError):
+        hm.adjoint_solve(g, path.mask, g.clone())         # needs an FP64 handle
 
 
 def test_save_load_replays_an_increment_bit_exactly(lib):

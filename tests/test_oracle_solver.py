@@ -70,6 +70,57 @@ def test_linear_elastic_solve_matches_dense_galerkin_assembly():
     assert np.allclose(F.reshape(shape + (3, 3)), F_ref, rtol=0, atol=1e-15 + 1e-11 * np.abs(F_bar).max())
 
 
+def _flat_project(shape):
+    V = int(np.prod(shape))
+
+    def project(A, mask):
+        return spectral.project(A.reshape(tuple(shape) + (3, 3)), mask).reshape(V, 3, 3)
+    return project
+
+
+def test_adjoint_operator_is_the_transpose_of_the_forward_operator():
+    """<y, G(K:x)> = <G(K^T:y), x> for a random non-symmetric K and random x, y in the range of
+    G (where the solves act), with either zero-frequency rule: fixes the index order of K^T
+    (a plain G(K:y) fails by the asymmetry)."""
+    shape = (4, 6, 5)
+    V = int(np.prod(shape))
+    rng = np.random.default_rng(7)
+    K = rng.standard_normal((V, 3, 3, 3, 3))
+    x = rng.standard_normal((V, 3, 3))
+    y = rng.standard_normal((V, 3, 3))
+    project = _flat_project(shape)
+    for mask in (np.ones(9), np.array([1, 1, 1, 1, 0, 1, 1, 1, 0])):
+        x, y = project(x, mask), project(y, mask)
+        fwd = project(np.einsum("vijkl,vkl->vij", K, x), mask)
+        adj = solver.adjoint_operator(project, K, mask)(y)
+        lhs, rhs = np.sum(y * fwd), np.sum(adj * x)
+        assert abs(lhs - rhs) <= 1e-12 * np.sqrt(np.sum(y * y) * np.sum(fwd * fwd))
+        wrong = project(np.einsum("vijkl,vkl->vij", K, y), mask)
+        assert abs(np.sum(wrong * x) - lhs) > 1e-3 * abs(lhs)
+
+
+def test_adjoint_solve_satisfies_the_transposed_system():
+    """For an elastic-like tangent made non-symmetric, the adjoint CG solution solves
+    G(K^T : lam) = G(g) (dense check of the residual) and differs from the solution with K."""
+    shape = (4, 4, 4)
+    V = 64
+    rve = synth.voronoi_rve(43, shape, 2, 1e-6, synth.material("Cu"))
+    R = elasticity.quat_to_matrix(rve.quats)
+    C0 = elasticity.cubic_stiffness(*synth.WORKLOAD_ELASTIC["Cu"])
+    K = elasticity.rotate4(C0, R)[rve.grain_of_voxel].reshape(V, 3, 3, 3, 3).copy()
+    rng = np.random.default_rng(11)
+    K += 0.05 * np.abs(C0).max() * rng.standard_normal(K.shape) * (rng.random(K.shape) < 0.1)
+    g = rng.standard_normal((V, 3, 3))
+    mask = np.array([1, 1, 1, 1, 0, 1, 1, 1, 0])
+    project = _flat_project(shape)
+    lam, it = solver.adjoint_solve(project, K, g, mask, 1e-13, 3000)
+    res = solver.adjoint_operator(project, K, mask)(lam) - project(g, mask)
+    assert np.sqrt(np.sum(res * res)) <= 1e-10 * np.sqrt(np.sum(project(g, mask) ** 2))
+    lam_k, _ = solver.conjugate_gradient(lambda y: project(np.einsum("vijkl,vkl->vij", K, y), mask),
+                                         project(g, mask), 1e-13, 3000)
+    assert np.sqrt(np.sum((lam_k - lam) ** 2)) > 1e-3 * np.sqrt(np.sum(lam * lam))
+
+
 @pytest.fixture(scope="module")
 def small_run():
     rves, path = synth.workload("cu64", n_override=6, n_inc_override=50)
