@@ -12,7 +12,8 @@ Modules
   spectral      rotated-scheme frequencies, projection operator, spectral curl (App. A, B)
   constitutive  finite-strain SGCP material point (eqs. 1-9, 14)
   solver        Galerkin-FFT Newton / conjugate-gradient homogenization (eqs. 15-18)
-  nye           Nye tensor and minimum-norm GND densities (eqs. 10-13, App. B)
+  nye           Nye tensor and minimum-norm GND densities (eqs. 10-13, App. B), and the
+                transpose of that chain (adjoint form)
   reference     independent reference solutions used to pin the above
                 (material point, laminate, dense Galerkin solve)
 
