@@ -223,6 +223,21 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
                           double* nye, const int32_t* gid, int32_t n_grains,
                           const double* grain_quat, double burgers, double* rho_gnd, void* stream);
 
+/* Reverse of the chain Fp -> Nye tensor -> GND densities (eqs. 10-13 and eq. 12 with the
+ * rotated-scheme derivative of Appendix A) for the adjoint form: given rho_bar = dL/d rho_GND
+ * (device, 12 x nvox), writes Fp_bar = dL/d Fp (device, 9 x nvox) and, when nye_bar is not
+ * NULL, nye_bar = dL/d alpha (device, 9 x nvox).  nye is the Nye tensor at which the chain is
+ * linearised (device, 9 x nvox, as written by rve_spectral_curl); the absolute values of the
+ * per-system densities take the sign of each segment density (0 at a zero density).  gid
+ * (device, nvox) holds grain ids in [0, n_grains); grain_quat (host, 4 x n_grains) the grain
+ * orientations; burgers > 0 and h > 0 as for rve_spectral_curl.  All device buffers belong to
+ * the caller and must not overlap.  The call allocates its own scratch, runs on stream (or the
+ * null stream) and returns after the stream has finished.  RVE_EINVAL for a null pointer, a
+ * non-positive h, burgers or n_grains. */
+int32_t rve_gnd_adjoint(const int32_t n[3], int32_t precision, double h, const double* nye,
+                        const int32_t* gid, int32_t n_grains, const double* grain_quat, double burgers,
+                        const double* rho_bar, double* nye_bar, double* Fp_bar, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

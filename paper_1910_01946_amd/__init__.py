@@ -16,7 +16,7 @@ from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rv
                    rve_options, rve_step_stats)
 
 __all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
-           "spectral_curl", "LibraryMissing", "RVEError", "lib"]
+           "spectral_curl", "gnd_adjoint", "LibraryMissing", "RVEError", "lib"]
 
 FIELDS = {"F": (0, 9), "P": (1, 9), "Fp": (2, 9), "rho_ssd": (3, 12), "rho_gnd": (4, 12),
           "nye": (5, 9), "dg": (6, 12)}
@@ -176,3 +176,13 @@ def spectral_curl(n, h, Fp, nye, gid=None, quats=None, burgers=0.0, rho_gnd=None
     check(lib().rve_spectral_curl(nn, precision, float(h), _ptr(Fp), _ptr(nye), _ptr(gid),
                                   0 if q is None else int(q.shape[0]), _dp(q) if q is not None else None,
                                   float(burgers), _ptr(rho_gnd), _stream(stream)))
+
+
+def gnd_adjoint(n, h, nye, gid, quats, burgers, rho_bar, Fp_bar, nye_bar=None, precision=RVE_FP64,
+                stream=None):
+    """Fp_bar (and nye_bar when given) = transpose of d rho_GND / d Fp at the Nye tensor nye,
+    applied to rho_bar; device tensors in the component-major layout of spectral_curl."""
+    nn = (C.c_int32 * 3)(*[int(v) for v in n])
+    q = np.ascontiguousarray(quats, dtype=np.float64)
+    check(lib().rve_gnd_adjoint(nn, precision, float(h), _ptr(nye), _ptr(gid), int(q.shape[0]), _dp(q),
+                                float(burgers), _ptr(rho_bar), _ptr(nye_bar), _ptr(Fp_bar), _stream(stream)))

@@ -1,0 +1,19 @@
+// Launchers of the reverse of the Nye tensor / GND chain (eqs. 10-13, eq. B.3).
+#ifndef RVE_ADJOINT_H
+#define RVE_ADJOINT_H
+
+#include "kernels.h"
+
+namespace rve {
+
+// alpha_bar (9 x nv, component-major) = (d rho_GND / d alpha)^T rho_bar (12 x nv) at the
+// Nye tensor nye (9 x nv); grain rotations grainR (9 per grain, sample <- crystal).
+void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const double* grainR,
+                        const MatDev* mat, const double* rho_bar, double* alpha_bar, hipStream_t st);
+
+// out(c, z, y, x) = in(c, z - 1, y - 1, x - 1) with periodic wrap, 9 components.
+void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st);
+
+}  // namespace rve
+
+#endif

@@ -1,0 +1,95 @@
+// Reverse of the chain Fp -> alpha -> rho_GND (eqs. 10-13 and the curl of eq. B.3) for
+// the adjoint form: given rho_bar = dL/d rho_GND, produce dL/d alpha and dL/d Fp.
+//
+//   k_gnd_adjoint   per voxel: alpha_c = R^T alpha R, segment densities rho = A^+ alpha_c / b,
+//                   u = sign(rho) * (system weights: 1 for the edge segment of each system,
+//                   1/2 for its screw segment, summed over the two systems sharing it),
+//                   alpha_bar = R ((A^+)^T u / b) R^T.  sign(0) = 0.
+//   curl transpose  the rotated-scheme derivative i k / h is a difference at the voxel corner
+//                   x + h/2 (1,1,1); its transpose has the symbol conj(i k / h) and, since
+//                   conj(k) = k exp(-i (xi_x + xi_y + xi_z)), the transposed curl equals the
+//                   curl itself taken one voxel back along every axis.  The spectral curl
+//                   kernels are reused unchanged and k_roll_back applies the shift.
+#include "adjoint.h"
+
+#include "common.h"
+
+namespace rve {
+
+namespace {
+
+__device__ __forceinline__ double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+
+__global__ void k_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const double* grainR,
+                              const MatDev* mat, const double* rho_bar, double* alpha_bar) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const MatDev& M = *mat;
+  double q[9], Rg[9], ac[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) q[c] = nye[c * nv + v];
+  const int gi = gid[v];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rg[i] = grainR[9 * gi + i];
+  to_crystal(Rg, q, ac);
+  double u[18];
+#pragma unroll
+  for (int s = 12; s < 18; ++s) u[s] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const double rb = rho_bar[a * nv + v];
+    const int k = M.screw_of[a];
+    u[a] = rb;
+    // static register indices: the screw segment is selected, not indexed
+#pragma unroll
+    for (int s = 0; s < 6; ++s) u[12 + s] += k == s ? 0.5 * rb : 0.0;
+  }
+  const double ib = 1.0 / M.burgers;
+#pragma unroll
+  for (int s = 0; s < 18; ++s) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) t += M.Aplus[s * 9 + c] * ac[c];
+    u[s] *= sgn(t) * ib;
+  }
+  double cb[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < 18; ++s) t += M.Aplus[s * 9 + c] * u[s];
+    cb[c] = t;
+  }
+  to_sample(Rg, cb, q);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) alpha_bar[c * nv + v] = q[c];
+}
+
+__global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* out) {
+  const int64_t plane = (int64_t)nx * ny, nv = plane * nz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 9 * nv) return;
+  const int64_t c = i / nv, r = i - c * nv;
+  const int z = (int)(r / plane);
+  const int64_t t = r - z * plane;
+  const int y = (int)(t / nx), x = (int)(t - (int64_t)y * nx);
+  const int zs = z == 0 ? nz - 1 : z - 1, ys = y == 0 ? ny - 1 : y - 1, xs = x == 0 ? nx - 1 : x - 1;
+  out[i] = in[c * nv + zs * plane + (int64_t)ys * nx + xs];
+}
+
+}  // namespace
+
+void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const double* grainR,
+                        const MatDev* mat, const double* rho_bar, double* alpha_bar, hipStream_t st) {
+  const int bs = 128;
+  hipLaunchKernelGGL(k_gnd_adjoint, dim3((unsigned)((nv + bs - 1) / bs)), dim3(bs), 0, st, nv, nye, gid, grainR,
+                     mat, rho_bar, alpha_bar);
+}
+
+void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st) {
+  const int bs = 256;
+  const int64_t n = 9 * (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_roll_back, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, nx, ny, nz, in, out);
+}
+
+}  // namespace rve

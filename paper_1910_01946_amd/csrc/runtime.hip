@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/rve.h"
+#include "adjoint.h"
 #include "kernels.h"
 #include "spectral.h"
 
@@ -1667,6 +1668,82 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
     }
     launch_xinv(g, fp32, xi, st);
     check_launch("curl");
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_gnd_adjoint(const int32_t n[3], int32_t precision, double h, const double* nye, const int32_t* gid,
+                        int32_t n_grains, const double* grain_quat, double burgers, const double* rho_bar,
+                        double* nye_bar, double* Fp_bar, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!n || !nye || !gid || !grain_quat || !rho_bar || !Fp_bar) throw Error(RVE_EINVAL, "null argument");
+    if (n_grains < 1) throw Error(RVE_EINVAL, "n_grains must be >= 1");
+    if (!(std::isfinite(h) && h > 0)) throw Error(RVE_EINVAL, "h must be > 0");
+    if (!(std::isfinite(burgers) && burgers > 0)) throw Error(RVE_EINVAL, "burgers must be > 0");
+    prepare_device();
+    const bool fp32 = precision == RVE_MIXED;
+    hipStream_t st = (hipStream_t)stream;
+    Plan P;
+    build_plan(P, n, fp32);
+    const GridPlan& g = P.g;
+    const size_t f9 = sizeof(double) * 9 * (size_t)g.nvox;
+    DevBuf spec, dmat, dR, abar, curl;
+    spec.alloc(tsize(fp32) * 2 * 9 * g.nspec);
+    curl.alloc(f9);
+    double* ab = nye_bar;
+    if (!ab) {
+      abar.alloc(f9);
+      ab = abar.as<double>();
+    }
+    MatDev md;
+    std::memset(&md, 0, sizeof(md));
+    md.burgers = burgers;
+    segment_pinv(md.Aplus, md.screw_of);
+    std::vector<double> Rg(9 * (size_t)n_grains);
+    for (int gi = 0; gi < n_grains; ++gi) quat_to_R(grain_quat + 4 * gi, &Rg[9 * gi]);
+    upload(dmat, &md, sizeof(md));
+    upload(dR, Rg.data(), sizeof(double) * Rg.size());
+    launch_gnd_adjoint(g.nvox, nye, gid, dR.as<double>(), dmat.as<MatDev>(), rho_bar, ab, st);
+    // transposed curl: the forward spectral curl of alpha_bar, then one voxel back per axis
+    const bool plane = plane_enabled() && plane_fits(g, fp32);
+    if (plane) {
+      PlaneArgs pa{PF_F64, ab, spec.p};
+      launch_plane_fwd(g, fp32, pa, nullptr, st);
+    } else {
+      XFwdArgs xf;
+      std::memset(&xf, 0, sizeof(xf));
+      xf.mode = XF_FIELD64;
+      xf.in64 = ab;
+      xf.spec = spec.p;
+      launch_xfwd(g, fp32, xf, st);
+      launch_yfft(g, fp32, spec.p, -1, nullptr, st);
+    }
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_CURL;
+    m.spec = spec.p;
+    m.inv_n = 1.0 / (double)g.nvox;
+    m.inv_h = 1.0 / h;
+    launch_mid(g, fp32, m, st);
+    if (plane) {
+      PlaneInvArgs pi;
+      std::memset(&pi, 0, sizeof(pi));
+      pi.mode = PI_OUT64;
+      pi.spec = spec.p;
+      pi.out64 = curl.as<double>();
+      launch_plane_inv(g, fp32, pi, st);
+    } else {
+      launch_yfft(g, fp32, spec.p, +1, nullptr, st);
+      XInvArgs xi;
+      std::memset(&xi, 0, sizeof(xi));
+      xi.mode = XI_OUT64;
+      xi.spec = spec.p;
+      xi.out64 = curl.as<double>();
+      launch_xinv(g, fp32, xi, st);
+    }
+    launch_roll_back(g.nx, g.ny, g.nz, curl.as<double>(), Fp_bar, st);
+    check_launch("gnd adjoint");
     HIPCHECK(hipStreamSynchronize(st));
     return RVE_OK;
   });

@@ -36,3 +36,25 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/librve.so")
     with pytest.raises(_lib.LibraryMissing):
         _lib.lib()
+
+
+def test_gnd_adjoint_rejects_bad_arguments_before_any_device_call():
+    """The argument checks of rve_gnd_adjoint run on the host: no GPU is needed to see them."""
+    from paper_1910_01946_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    L = _lib.lib()
+    n = (ctypes.c_int32 * 3)(4, 4, 4)
+    q = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 0.0)
+    fake = ctypes.c_void_p(16)   # never dereferenced: every call below fails its host checks
+    cases = [
+        (None, 1, 1.0, 0.25e-9, fake),    # null nye
+        (fake, 0, 1.0, 0.25e-9, fake),    # no grains
+        (fake, 1, 0.0, 0.25e-9, fake),    # h = 0
+        (fake, 1, 1.0, -1.0, fake),       # negative Burgers vector
+        (fake, 1, 1.0, 0.25e-9, None),    # null Fp_bar
+    ]
+    for nye, ng, h, b, out in cases:
+        rc = L.rve_gnd_adjoint(n, 0, h, nye, fake, ng, q, b, fake, None, out, None)
+        assert rc == -1
+        assert L.rve_last_error()

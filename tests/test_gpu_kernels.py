@@ -108,3 +108,33 @@ def test_curl_and_gnd_match_oracle(lib, shape, plane, monkeypatch):
     torch.cuda.synchronize()
     assert rel_norm(from_abi(nye.cpu().numpy()), alpha.reshape(V, 3, 3)) < 1e-13
     assert rel_norm(from_abi(rg.cpu().numpy(), tensor=False), rho.reshape(V, 12)) < 1e-12
+
+
+@pytest.mark.parametrize("shape,precision", [((8, 8, 8), 0), ((6, 10, 4), 0), ((32, 32, 32), 0),
+                                             ((32, 32, 32), 1)])
+@pytest.mark.parametrize("plane", ["1", "0"])
+def test_gnd_adjoint_matches_oracle(lib, shape, precision, plane, monkeypatch):
+    """Transpose of Fp -> alpha -> rho_GND applied to a random rho_bar, at the oracle's Nye
+    tensor: alpha_bar per voxel (FP64 on both sides) and Fp_bar through the transposed curl
+    (FP64, or FP32 spectra in the mixed form)."""
+    monkeypatch.setenv("RVE_PLANE", plane)
+    import torch
+    nx, ny, nz = shape
+    V = nx * ny * nz
+    b = 0.256e-9
+    h = 2.5e-6
+    rve = synth.voronoi_rve(17, shape, 5, 1e-6, synth.material("Cu"))
+    Fp = np.eye(3) + 1e-3 * synth.random_field(18, (nz, ny, nx, 3, 3))
+    rho_bar = synth.random_field(19, (nz, ny, nx, 12))
+    alpha = onye.nye_tensor(Fp, h)
+    alpha_bar, Fp_bar = onye.gnd_fp_adjoint(Fp, h, rve.grain_of_voxel, rve.quats, b, rho_bar)
+    nye_bar = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    out = torch.full((9, V), float("nan"), dtype=torch.float64, device="cuda:0")
+    print(f"gnd adjoint shape={shape} precision={precision} plane={plane}", flush=True)
+    lib.gnd_adjoint(shape, h, cuda(to_abi(alpha.reshape(V, 3, 3))), cuda(rve.grain_of_voxel.reshape(-1)),
+                    rve.quats, b, cuda(np.ascontiguousarray(rho_bar.reshape(V, 12).T)), out, nye_bar=nye_bar,
+                    precision=precision)
+    torch.cuda.synchronize()
+    assert rel_norm(from_abi(nye_bar.cpu().numpy()), alpha_bar.reshape(V, 3, 3)) < 1e-13
+    tol = 1e-12 if precision == 0 else 2e-6
+    assert rel_norm(from_abi(out.cpu().numpy()), Fp_bar.reshape(V, 3, 3)) < tol
