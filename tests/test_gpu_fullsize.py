@@ -1,7 +1,9 @@
-"""Parity at the benchmark's full size (64^3, 64 grains, strain-gradient Cu) in the launch
-configuration the benchmark times (mixed precision, performance tolerances).  The oracle
-cannot run the whole increment at this size, so it checks sampled outputs one by one and
-properties that hold at any size (GPU only)."""
+"""Parity at the benchmark workloads' full sizes in the launch configuration the benchmark
+times (mixed precision, performance tolerances): cu64 (64^3, 64 grains, strain-gradient
+Cu), al128 (128^3, 200 grains, Al), cu64g100 (64^3, 100 grains) and sweep32 (32 RVEs of
+uneven size in one handle; five of them are checked).  The oracle cannot run a whole
+increment at these sizes, so it checks sampled outputs one by one and properties that hold
+at any size (GPU only)."""
 import numpy as np
 import pytest
 
@@ -12,33 +14,41 @@ from tests.gpu_util import from_abi, rel_norm
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def run():
+def _checked(rves):
+    """RVEs of a batch that the oracle checks: the first two, the smallest and the largest."""
+    sizes = [r.n_vox for r in rves]
+    pick = [0, 1, len(rves) - 1, int(np.argmin(sizes)), int(np.argmax(sizes))]
+    return sorted({i for i in pick if i < len(rves)})
+
+
+@pytest.fixture(scope="module", params=["cu64", "al128", "cu64g100", "sweep32"])
+def run(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1910_01946_amd as lib
     lib.lib()
-    rves, path = synth.workload("cu64")
-    rve = rves[0]
+    name = request.param
+    rves, path = synth.workload(name)
     h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3, max_cg=3000, max_newton=150)
     for k in (1, 2):
-        print(f"cu64 increment {k}", flush=True)
+        print(f"{name} increment {k}", flush=True)
         h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
-    start = {n: from_abi(h.field(n), tensor=(n in ("F", "Fp"))) for n in ("Fp", "rho_ssd", "rho_gnd")}
-    print("cu64 increment 3", flush=True)
-    st = h.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)[0]
-    end = {n: from_abi(h.field(n), tensor=(n in ("F", "P", "Fp", "nye")))
-           for n in ("F", "P", "Fp", "rho_ssd", "rho_gnd", "nye", "dg")}
-    macro = h.macro()
+    idx = _checked(rves)
+    start = {i: {n: from_abi(h.field(n, i), tensor=(n in ("F", "Fp"))) for n in ("Fp", "rho_ssd", "rho_gnd")}
+             for i in idx}
+    print(f"{name} increment 3", flush=True)
+    st = h.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)
+    out = []
+    for i in idx:
+        end = {n: from_abi(h.field(n, i), tensor=(n in ("F", "P", "Fp", "nye")))
+               for n in ("F", "P", "Fp", "rho_ssd", "rho_gnd", "nye", "dg")}
+        out.append((rves[i], path, start[i], end, st[i], h.macro(i)))
     h.close()
-    return rve, path, start, end, st, macro
+    return out
 
 
-def test_sampled_constitutive_points_match_oracle(run):
-    """At 256 seeded voxels, the oracle's update from the GPU's converged F and the
-    start-of-increment state reproduces the GPU's P, slip increments, Fp and rho_SSD."""
-    rve, path, start, end, st, _ = run
+def _sampled_constitutive_points(rve, path, start, end):
     V = rve.n_vox
     rng = synth.SplitMix64(77)
     idx = np.unique((np.array([rng.uniform() for _ in range(256)]) * V).astype(int))
@@ -53,42 +63,50 @@ def test_sampled_constitutive_points_match_oracle(run):
     assert rel_norm(end["rho_ssd"][idx], out["rho_ssd"]) < 1e-12
 
 
+def test_sampled_constitutive_points_match_oracle(run):
+    """At 256 seeded voxels, the oracle's update from the GPU's converged F and the
+    start-of-increment state reproduces the GPU's P, slip increments, Fp and rho_SSD."""
+    for rve, path, start, end, _, _ in run:
+        print("constitutive samples", rve.n, rve.seed, flush=True)
+        _sampled_constitutive_points(rve, path, start, end)
+
+
 def test_nye_and_gnd_of_committed_fp_match_oracle(run):
     """Whole-field Nye tensor and GND densities of the committed Fp (FP32 spectral path
     in the mixed form: relative error of a few FP32 roundings of Fp - I)."""
-    rve, _, _, end, _, _ = run
-    shape = rve.grain_of_voxel.shape
-    alpha, _, rho = nye.gnd_from_fp(end["Fp"].reshape(shape + (3, 3)), rve.voxel_size, rve.grain_of_voxel,
-                                    rve.quats, rve.material.burgers)
-    err_a = rel_norm(end["nye"], alpha.reshape(-1, 3, 3))
-    err_r = rel_norm(end["rho_gnd"], rho.reshape(-1, 12))
-    print("nye", err_a, "rho_gnd", err_r, flush=True)
-    assert err_a < 2e-5 and err_r < 2e-5
+    for rve, _, _, end, _, _ in run:
+        shape = rve.grain_of_voxel.shape
+        alpha, _, rho = nye.gnd_from_fp(end["Fp"].reshape(shape + (3, 3)), rve.voxel_size, rve.grain_of_voxel,
+                                        rve.quats, rve.material.burgers)
+        err_a = rel_norm(end["nye"], alpha.reshape(-1, 3, 3))
+        err_r = rel_norm(end["rho_gnd"], rho.reshape(-1, 12))
+        print(rve.n, rve.seed, "nye", err_a, "rho_gnd", err_r, flush=True)
+        assert err_a < 2e-5 and err_r < 2e-5
 
 
 def test_converged_field_is_compatible_and_balanced(run):
     """F - <F> is a discrete gradient (the projection leaves it unchanged); the projected
     stress residual equals the one the GPU reports and is small against the stress; the
     stress-controlled averages vanish and the deformation-controlled ones hit the target."""
-    rve, path, _, end, st, macro = run
-    shape = rve.grain_of_voxel.shape
-    F = end["F"].reshape(shape + (3, 3))
-    P = end["P"].reshape(shape + (3, 3))
-    fluct = F - F.mean(axis=(0, 1, 2))
-    GF = spectral.project(F, np.ones(9))                 # every average dropped
-    incompat = rel_norm(GF, fluct)
-    print("incompatible part of F - <F>", incompat, flush=True)
-    # every Newton correction is projected in FP64 before it is applied, also in the mixed
-    # form, so F - <F> is a discrete gradient to FP64 rounding
-    assert incompat < 1e-10
-    r = spectral.project(P, path.mask, path.P_bar[3].reshape(3, 3))
-    rms_r = float(np.sqrt(np.mean(r * r)))
-    rms_P = float(np.sqrt(np.mean(P * P)))
-    print("residual rms", rms_r, "stress rms", rms_P, "reported", st["res_norm"], flush=True)
-    # the residual the GPU reports (FP32 spectral path) is the oracle's FP64 projection of
-    # the GPU's stress, and at a correction tolerance of 1e-6 it is a small part of the stress
-    assert abs(rms_r - st["res_norm"]) <= 1e-5 * rms_r
-    assert rms_r < 2e-3 * rms_P
-    P_avg = macro[0]
-    assert abs(P_avg[4]) < 1e-4 * abs(P_avg[0]) and abs(P_avg[8]) < 1e-4 * abs(P_avg[0])
-    assert np.allclose(macro[1], path.F_bar[3] * path.mask + macro[1] * (1 - path.mask), rtol=0, atol=1e-12)
+    for rve, path, _, end, st, macro in run:
+        shape = rve.grain_of_voxel.shape
+        F = end["F"].reshape(shape + (3, 3))
+        P = end["P"].reshape(shape + (3, 3))
+        fluct = F - F.mean(axis=(0, 1, 2))
+        GF = spectral.project(F, np.ones(9))                 # every average dropped
+        incompat = rel_norm(GF, fluct)
+        print(rve.n, rve.seed, "incompatible part of F - <F>", incompat, flush=True)
+        # every Newton correction is projected in FP64 before it is applied, also in the mixed
+        # form, so F - <F> is a discrete gradient to FP64 rounding
+        assert incompat < 1e-10
+        r = spectral.project(P, path.mask, path.P_bar[3].reshape(3, 3))
+        rms_r = float(np.sqrt(np.mean(r * r)))
+        rms_P = float(np.sqrt(np.mean(P * P)))
+        print("residual rms", rms_r, "stress rms", rms_P, "reported", st["res_norm"], flush=True)
+        # the residual the GPU reports (FP32 spectral path) is the oracle's FP64 projection of
+        # the GPU's stress, and at a correction tolerance of 1e-6 it is a small part of the stress
+        assert abs(rms_r - st["res_norm"]) <= 1e-5 * rms_r
+        assert rms_r < 2e-3 * rms_P
+        P_avg = macro[0]
+        assert abs(P_avg[4]) < 1e-4 * abs(P_avg[0]) and abs(P_avg[8]) < 1e-4 * abs(P_avg[0])
+        assert np.allclose(macro[1], path.F_bar[3] * path.mask + macro[1] * (1 - path.mask), rtol=0, atol=1e-12)
