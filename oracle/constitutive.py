@@ -316,3 +316,31 @@ def tangent_fd(model: MaterialModel, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg,
                 Ppm = stress(pd, Fpm, dgp)[0]
                 K[sl, :, :, kk, ll] = (Ppm[0::2] - Ppm[1::2]) / (2.0 * step)
     return K
+
+
+def stress_gnd_sensitivity_fd(model: MaterialModel, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg,
+                              rel_step=1e-4, chunk=4096):
+    """dP_ij / d rho_GND,n,b (V, 3, 3, 12) by central differences of the converged update in the
+    start-of-increment GND densities, which reach the stress only through tau_c (eq. 7).  The
+    step of a voxel is rel_step times its largest density; each perturbed solve is warm-started
+    from the converged slip increments dg.  The stress moves by about 1e-7 of itself over the
+    default step, so the local solve's convergence bound limits the quotient to a few 1e-7;
+    the truncation error is of the same order."""
+    V = F.shape[0]
+    out = np.empty((V, 3, 3, 12))
+    for lo in range(0, V, chunk):
+        sl = slice(lo, min(V, lo + chunk))
+        scale = np.maximum(rho_ssd_n[sl].max(axis=1), rho_gnd_n[sl].max(axis=1))
+        step = rel_step * scale
+        F2 = np.repeat(F[sl], 2, axis=0)
+        dg2 = np.repeat(dg[sl], 2, axis=0)
+        for b in range(12):
+            rg = np.repeat(rho_gnd_n[sl], 2, axis=0)
+            rg[0::2, b] += step
+            rg[1::2, b] -= step
+            pd = PointData(model, np.repeat(gid[sl], 2), np.repeat(Fp_n[sl], 2, axis=0),
+                           np.repeat(rho_ssd_n[sl], 2, axis=0), rg)
+            dgp, _, _ = solve_slip(pd, F2, dt, dg2)
+            Ppm = stress(pd, F2, dgp)[0]
+            out[sl, :, :, b] = (Ppm[0::2] - Ppm[1::2]) / (2.0 * step[:, None, None])
+    return out

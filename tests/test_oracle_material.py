@@ -98,3 +98,19 @@ def test_schmid_single_crystal_steady_flow():
     assert np.sum(tau > 0.9 * tau.max()) == 8
     # the lateral stresses vanish
     assert abs(res[-1][1][1, 1]) < 1e-3 and abs(res[-1][1][2, 2]) < 1e-3
+
+
+def test_fd_gnd_sensitivity_step_consistency_and_zero_gradient_term():
+    """dP/d rho_GND by central differences: two steps agree (the difference quotient has
+    converged), and with c_GND = 0 the GND densities do not reach the stress at all."""
+    mat, model, gid, F, Fp_n, rs, rg = _setup(V=4)
+    dt = 0.5
+    out = cst.update(model, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    S1 = cst.stress_gnd_sensitivity_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], rel_step=1e-4)
+    S2 = cst.stress_gnd_sensitivity_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], rel_step=4e-4)
+    assert np.abs(S1).max() > 0
+    assert np.abs(S1 - S2).max() / np.abs(S1).max() < 2e-6
+    mat0, model0, *_ = _setup(V=4, c_gnd=0.0)
+    out0 = cst.update(model0, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    S0 = cst.stress_gnd_sensitivity_fd(model0, gid, F, Fp_n, rs, rg, dt, out0["dg"])
+    assert not S0.any()
