@@ -210,6 +210,20 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
                                const double* rho_gnd_n, double dt, double* dg, double* P,
                                double* K, int32_t* iters, void* stream);
 
+/* Sensitivity of the converged stress to the critical resolved shear stresses, for the
+ * adjoint form: dPdtc[(9c + r) * nvox + v] = dP_r / dtau_c,c (device out, 108 x nvox, FP64,
+ * sample frame), where r = 3i + j indexes P_ij.  tau_c (eq. 7) is held fixed over an increment,
+ * so the slip increments dg (device, 12 x nvox) must be the converged ones that
+ * rve_constitutive_batch returned for the same inputs; the root then moves by the implicit
+ * function theorem through the flow rule (eq. 6) and the stress follows through Fp (eqs. 2,
+ * 14).  Other arguments as for rve_constitutive_batch.  Gradients of a loss with respect to
+ * the hardening parameters follow by the chain rule through tau_c (eq. 7).  Errors: RVE_EINVAL
+ * for a null pointer or dt <= 0. */
+int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const double* grain_quat,
+                               int64_t nvox, const int32_t* gid, const double* F, const double* Fp_n,
+                               const double* rho_ssd_n, const double* rho_gnd_n, double dt,
+                               const double* dg, double* dPdtc, void* stream);
+
 /* Projection G of eq. 17 applied to a real FP64 field A (device, 9 x nvox, grid n) with
  * the mixed-control zero-frequency rule of mask (host, 9) and target dc_target (host, 9;
  * NULL = 0); result in out (device, 9 x nvox).  precision selects FP64 or FP32 spectra. */

@@ -16,7 +16,8 @@ from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rv
                    rve_options, rve_step_stats)
 
 __all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
-           "spectral_curl", "gnd_adjoint", "LibraryMissing", "RVEError", "lib"]
+           "spectral_curl", "gnd_adjoint", "stress_sensitivity",
+           "LibraryMissing", "RVEError", "lib"]
 
 FIELDS = {"F": (0, 9), "P": (1, 9), "Fp": (2, 9), "rho_ssd": (3, 12), "rho_gnd": (4, 12),
           "nye": (5, 9), "dg": (6, 12)}
@@ -159,6 +160,16 @@ def constitutive_batch(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, P
     check(lib().rve_constitutive_batch(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
                                        _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
                                        _ptr(dg), _ptr(P), _ptr(K), _ptr(iters), _stream(stream)))
+
+
+def stress_sensitivity(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, dPdtc, stream=None):
+    """dPdtc (108 x nvox, row 9c + r) = dP_r / dtau_c,c at the slip increments dg (torch device
+    tensors, component-major), for the adjoint form."""
+    q = np.ascontiguousarray(quats, dtype=np.float64)
+    m = make_material(mat)
+    check(lib().rve_stress_sensitivity(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
+                                       _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
+                                       _ptr(dg), _ptr(dPdtc), _stream(stream)))
 
 
 def project(n, A, mask, out, dc_target=None, precision=RVE_FP64, stream=None):

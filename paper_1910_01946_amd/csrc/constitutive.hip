@@ -30,6 +30,7 @@
 //   dtau_a = Fe_k. Chat_a G_l.  (G = Fp^{-1}),  ddg = J^{-1} (D dtau),  Z = sum_b ddg_b s_b (x) m_b,
 //   dEe = sym(Fe_k. (x) G_l.) - sym(Ce Z A^{-1}),  dS = C : dEe,
 //   dP = e_k (x) (G S G^T)_l. - Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T.
+#include "adjoint.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -451,6 +452,87 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
   }
 }
 
+// Sensitivity of the converged stress to the critical resolved shear stresses (eqs. 6, 7,
+// 14), for the adjoint form.  With tau_c fixed over the increment, R_a depends on tau_c,a
+// only through the flow rule: dR_a/dtau_c,a = n g_a / tau_c,a, where g_a = dg_a - R_a is the
+// flow value at the evaluated slip increments.  A unit change of tau_c,c moves the root by
+// ddg = -J^{-1} e_c n g_c / tau_c,c (implicit function theorem), and the stress responds through
+// Fp alone: Z = sum_b ddg_b s_b (x) m_b, dEe = -sym(Ce Z A^{-1}), dS = C : dEe,
+// dP = -Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T (the F-direction terms of the
+// tangent vanish).  Output in the sample frame, dPdtc[(9c + r) * nvox + v] = dP_r / dtau_c,c.
+__global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, double* dPdtc) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = args.nvox;
+  if (v >= nv) return;
+  const MatDev& M = *args.mat;
+  double Rg[9];
+  Point p;
+  ConstArgs a2 = args;
+  a2.F_out = nullptr;
+  setup_point(a2, M, v, nv, nullptr, Rg, p);
+  double dg[12];
+#pragma unroll
+  for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+  Kin k;
+  double R[12], D[12];
+  residual(p, M.n_exp, dg, k, R, D);
+  double G[9], SGt[9];
+  mm3(p.Gn, k.Ainv, G);            // Fp^{-1}
+  mmt3(k.S, G, SGt);               // S G^T
+  double J[12][12];
+  jacobian(p, k, D, J);
+  lu12(J);
+  double Q[9], W[9], AtS[9];
+  mm3(k.Ainv, SGt, Q);             // A^{-1} S G^T
+  mmt3(k.S, k.Ainv, AtS);          // S A^{-T}
+  mm3(k.Fe, AtS, W);               // Fe S A^{-T}
+#pragma unroll 1
+  for (int c = 0; c < 12; ++c) {
+    double x[12];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) x[a] = 0.0;
+    // static register indices: the right-hand side entry is selected, not indexed
+#pragma unroll
+    for (int a = 0; a < 12; ++a)
+      if (a == c) x[a] = -M.n_exp * (dg[a] - R[a]) / p.tc[a];
+    lu12_solve(J, x);
+    double Z[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double z = 0.0;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) z += x[b] * kSlipS[b][i] * kSlipM[b][j];
+        Z[3 * i + j] = z;
+      }
+    double CeZ[9], CeZA[9], dE[9], dS[9];
+    mm3(k.Ce, Z, CeZ);
+    mm3(CeZ, k.Ainv, CeZA);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dE[3 * i + j] = -0.5 * (CeZA[3 * i + j] + CeZA[3 * j + i]);
+    cubic_stress(p, dE, dS);
+    double t1[9], t2[9], dP[9], dPs[9];
+    mm3(Z, Q, t1);                 // - Fe Z Q
+    mm3(k.Fe, t1, dP);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dP[i] = -dP[i];
+    mmt3(dS, G, t1);               // + Fe dS G^T
+    mm3(k.Fe, t1, t2);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dP[i] += t2[i];
+    mm3(G, Z, t1);                 // - W (G Z)^T
+    mmt3(W, t1, t2);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
+    to_sample(Rg, dP, dPs);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) dPdtc[(int64_t)(9 * c + r) * nv + v] = dPs[r];
+  }
+}
+
 // Commit of an increment: Fp = (R A_c R^T) Fp_n and rho_SSD = rho_SSD,n + h |dg| (eq. 8),
 // h = (1/b)(1/l - 2 y_c rho_SSD,n), l = K / sqrt(sum_{b != a} (rho_SSD,n + c_gnd rho_GND,n)).
 __global__ void k_commit(CommitArgs args) {
@@ -539,6 +621,12 @@ void launch_constitutive(const ConstArgs& a, int ktype, hipStream_t st, LaunchTi
     else if (ktype == KT_F32) launch(k_stress_tangent<float>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
     else launch(k_stress_tangent<double>, dim3((unsigned)nb), dim3(bs), 0u, st, a);
   }
+}
+
+void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, hipStream_t st) {
+  const int bs = 64;
+  const int64_t nb = (a.nvox + bs - 1) / bs;
+  launch(k_stress_sensitivity, dim3((unsigned)nb), dim3(bs), 0u, st, a, dPdtc);
 }
 
 void launch_commit(const CommitArgs& a, hipStream_t st) {

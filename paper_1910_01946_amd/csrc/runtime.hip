@@ -1574,6 +1574,41 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
   });
 }
 
+int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const double* grain_quat, int64_t nvox,
+                               const int32_t* gid, const double* F, const double* Fp_n, const double* rho_ssd_n,
+                               const double* rho_gnd_n, double dt, const double* dg, double* dPdtc,
+                               void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!mat || n_grains < 1 || !grain_quat || nvox < 1 || !gid || !F || !Fp_n || !rho_ssd_n || !rho_gnd_n || !dg ||
+        !dPdtc)
+      throw Error(RVE_EINVAL, "null argument");
+    if (!(std::isfinite(dt) && dt > 0)) throw Error(RVE_EINVAL, "dt must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    MatDev md = make_material(*mat);
+    std::vector<double> Rg(9 * (size_t)n_grains);
+    for (int g = 0; g < n_grains; ++g) quat_to_R(grain_quat + 4 * g, &Rg[9 * g]);
+    DevBuf dmat, dR;
+    upload(dmat, &md, sizeof(md));
+    upload(dR, Rg.data(), sizeof(double) * Rg.size());
+    ConstArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nvox = nvox;
+    a.gid = gid;
+    a.grainR = dR.as<double>();
+    a.mat = dmat.as<MatDev>();
+    a.F = F;
+    a.Fp_n = Fp_n;
+    a.rho_ssd = rho_ssd_n;
+    a.rho_gnd = rho_gnd_n;
+    a.dg = const_cast<double*>(dg);   // read only
+    a.dt = dt;
+    launch_stress_sensitivity(a, dPdtc, st);
+    check_launch("stress sensitivity");
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
 int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
                     const double* dc_target, double* out, void* stream) {
   return guarded([&]() -> int32_t {

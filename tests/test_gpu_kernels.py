@@ -65,6 +65,44 @@ def test_constitutive_update_and_tangent(lib, amp, hard):
     assert err.max() < 2e-5
 
 
+@pytest.mark.parametrize("amp", [3e-4, 2e-3])
+def test_stress_sensitivity_matches_oracle_differences(lib, amp):
+    """dP/dtau_c from the implicit function theorem, chained through eq. 7 to the
+    start-of-increment GND densities (d tau_c,a / d rho_GND,b = c_GND (mu b)^2 q_ab / (2 tau_c,a)),
+    against central differences of the oracle's update in those densities, at the oracle's
+    converged slip increments.  At nearly elastic voxels (slip increments of 1e-11 to 1e-7)
+    the difference quotient carries rounding noise that grows as the step shrinks; each
+    voxel's bar is 2e-5 plus the oracle's own error estimate there (the change of the
+    quotient between steps of 4e-4 and 1e-4), and most voxels must meet 2e-5 alone."""
+    import torch
+    mat = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=1)
+    V = 300
+    q, model, gid, F, Fp_n, rs, rg, dg0 = _points(V, amp, 23, mat)
+    dt = 0.5
+    ref = cst.update(model, gid, F, Fp_n, rs, rg, dt, dg0)
+    assert ref["converged"].all()
+    S_ref = cst.stress_gnd_sensitivity_fd(model, gid, F, Fp_n, rs, rg, dt, ref["dg"], rel_step=4e-4)
+    S_fine = cst.stress_gnd_sensitivity_fd(model, gid, F, Fp_n, rs, rg, dt, ref["dg"], rel_step=1e-4)
+    out = torch.zeros((108, V), dtype=torch.float64, device="cuda:0")
+    print(f"stress sensitivity V={V} amp={amp}", flush=True)
+    lib.stress_sensitivity(mat, q, cuda(gid), cuda(to_abi(F)), cuda(to_abi(Fp_n)), cuda(to_abi(rs)),
+                           cuda(to_abi(rg)), dt, cuda(to_abi(ref["dg"])), out)
+    torch.cuda.synchronize()
+    dPdtc = out.cpu().numpy().reshape(12, 9, V).transpose(2, 1, 0)                          # (V, 9, 12)
+    mub2 = (model.mu * mat.burgers) ** 2
+    dtc = mat.c_gnd * mub2 * model.q[None, :, :] / (2.0 * ref["tau_c"][:, :, None])          # (V, a, b)
+    S = np.einsum("vra,vab->vrb", dPdtc, dtc).reshape(V, 3, 3, 12)
+    ref_max = np.abs(S_ref).reshape(V, -1).max(axis=1)
+    norm = ref_max + 1e-3 * ref_max.max()
+    err = np.abs(S - S_ref).reshape(V, -1).max(axis=1) / norm
+    est = np.abs(S_fine - S_ref).reshape(V, -1).max(axis=1) / norm
+    print("max relative difference", err.max(), "largest oracle error estimate", est.max(),
+          "voxels within 2e-5", int((err < 2e-5).sum()), flush=True)
+    assert ref_max.max() > 0
+    assert np.all(err < 2e-5 + 2.0 * est)
+    assert (err < 2e-5).mean() >= 0.95
+
+
 @pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 4), (10, 12, 6), (16, 16, 16), (64, 64, 64),
                                    (40, 48, 24), (96, 80, 6), (128, 128, 4)])
 @pytest.mark.parametrize("precision", [0, 1])
