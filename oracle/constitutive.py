@@ -344,3 +344,25 @@ def stress_gnd_sensitivity_fd(model: MaterialModel, gid, F, Fp_n, rho_ssd_n, rho
             Ppm = stress(pd, F2, dgp)[0]
             out[sl, :, :, b] = (Ppm[0::2] - Ppm[1::2]) / (2.0 * step[:, None, None])
     return out
+
+
+def density_param_sensitivity_fd(model: MaterialModel, gid, Fp_n, rho_ssd_n, rho_gnd_n, dg,
+                                 rel_step=1e-4):
+    """d rho_SSD / d K (row 0) and d rho_SSD / d y_c (row 1), (V, 2, 12), of the density update
+    (eqs. 8-9) at fixed slip increments dg, by central differences of the material parameters.
+    K and y_c do not reach the slip solve of the same increment (tau_c uses the
+    start-of-increment densities), so dg stays fixed."""
+    import copy
+    import dataclasses
+    mat = model.mat
+    out = np.empty((rho_ssd_n.shape[0], 2, 12))
+    for row, name in enumerate(("K_sim", "y_c")):
+        base = getattr(mat, name)
+        step = rel_step * abs(base)
+        rho = []
+        for sign in (1.0, -1.0):
+            m2 = copy.copy(model)
+            m2.mat = dataclasses.replace(mat, **{name: base + sign * step})
+            rho.append(_rho_ssd(PointData(m2, gid, Fp_n, rho_ssd_n, rho_gnd_n), dg))
+        out[:, row, :] = (rho[0] - rho[1]) / (2.0 * step)
+    return out

@@ -114,3 +114,24 @@ def test_fd_gnd_sensitivity_step_consistency_and_zero_gradient_term():
     out0 = cst.update(model0, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
     S0 = cst.stress_gnd_sensitivity_fd(model0, gid, F, Fp_n, rs, rg, dt, out0["dg"])
     assert not S0.any()
+
+
+def test_fd_density_parameter_sensitivity():
+    """d rho_SSD / d(K, y_c) of eq. 8 by central differences: y_c enters linearly, so two steps
+    agree to rounding; the K quotient has converged; without hardening both vanish exactly."""
+    mat, model, gid, F, Fp_n, rs, rg = _setup(V=6)
+    dt = 0.5
+    out = cst.update(model, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    S1 = cst.density_param_sensitivity_fd(model, gid, Fp_n, rs, rg, out["dg"], rel_step=1e-4)
+    S2 = cst.density_param_sensitivity_fd(model, gid, Fp_n, rs, rg, out["dg"], rel_step=4e-4)
+    for row, bar in ((0, 1e-6), (1, 1e-9)):
+        assert np.abs(S1[:, row]).max() > 0
+        assert np.abs(S1[:, row] - S2[:, row]).max() <= bar * np.abs(S1[:, row]).max()
+    # no slip on a system, no change of its density with either parameter
+    dg = out["dg"].copy()
+    dg[:, 3] = 0.0
+    S3 = cst.density_param_sensitivity_fd(model, gid, Fp_n, rs, rg, dg)
+    assert not S3[:, :, 3].any()
+    mat0 = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=0)
+    model0 = cst.MaterialModel(mat0, synth.shoemake_quaternions(synth.SplitMix64(3), 4))
+    assert not cst.density_param_sensitivity_fd(model0, gid, Fp_n, rs, rg, out["dg"]).any()
