@@ -224,6 +224,16 @@ int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const 
                                const double* rho_ssd_n, const double* rho_gnd_n, double dt,
                                const double* dg, double* dPdtc, void* stream);
 
+/* Sensitivity of the SSD density update (eqs. 8-9) to its parameters, for the adjoint form:
+ * out[a * nvox + v] = d rho_SSD,a / dK and out[(12 + a) * nvox + v] = d rho_SSD,a / dy_c
+ * (device out, 24 x nvox, FP64) at fixed slip increments dg (device, 12 x nvox), from the
+ * start-of-increment densities rho_ssd_n, rho_gnd_n (device, 12 x nvox each).  K and y_c do not
+ * reach the slip solve of the same increment (tau_c uses the start-of-increment densities),
+ * so these are the whole derivatives of the committed densities.  Zero for a material without
+ * hardening.  Errors: RVE_EINVAL for a null pointer, nvox < 1 or an invalid material. */
+int32_t rve_density_sensitivity(const rve_material* mat, int64_t nvox, const double* rho_ssd_n,
+                                const double* rho_gnd_n, const double* dg, double* out, void* stream);
+
 /* Projection G of eq. 17 applied to a real FP64 field A (device, 9 x nvox, grid n) with
  * the mixed-control zero-frequency rule of mask (host, 9) and target dc_target (host, 9;
  * NULL = 0); result in out (device, 9 x nvox).  precision selects FP64 or FP32 spectra. */

@@ -16,7 +16,7 @@ from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rv
                    rve_options, rve_step_stats)
 
 __all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
-           "spectral_curl", "gnd_adjoint", "stress_sensitivity",
+           "spectral_curl", "gnd_adjoint", "stress_sensitivity", "density_sensitivity",
            "LibraryMissing", "RVEError", "lib"]
 
 FIELDS = {"F": (0, 9), "P": (1, 9), "Fp": (2, 9), "rho_ssd": (3, 12), "rho_gnd": (4, 12),
@@ -170,6 +170,14 @@ def stress_sensitivity(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, d
     check(lib().rve_stress_sensitivity(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
                                        _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
                                        _ptr(dg), _ptr(dPdtc), _stream(stream)))
+
+
+def density_sensitivity(mat, rho_ssd_n, rho_gnd_n, dg, out, stream=None):
+    """out (24 x nvox): d rho_SSD / dK (rows 0-11) and d rho_SSD / dy_c (rows 12-23) of the
+    density update at fixed slip increments dg (torch device tensors, component-major)."""
+    m = make_material(mat)
+    check(lib().rve_density_sensitivity(C.byref(m), int(dg.shape[1]), _ptr(rho_ssd_n), _ptr(rho_gnd_n),
+                                        _ptr(dg), _ptr(out), _stream(stream)))
 
 
 def project(n, A, mask, out, dc_target=None, precision=RVE_FP64, stream=None):

@@ -16,6 +16,11 @@ void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const
 // slip increments a.dg (constitutive.hip).
 void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, hipStream_t st);
 
+// out (24 x nv): d rho_SSD,a / dK (row a) and d rho_SSD,a / dy_c (row 12 + a) of eqs. 8-9 at
+// fixed slip increments dg (12 x nv), from the start-of-increment densities.
+void launch_density_sensitivity(int64_t nv, const MatDev* mat, const double* rho_ssd, const double* rho_gnd,
+                                const double* dg, double* out, hipStream_t st);
+
 // out(c, z, y, x) = in(c, z - 1, y - 1, x - 1) with periodic wrap, 9 components.
 void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st);
 

@@ -1,5 +1,6 @@
-// Reverse of the chain Fp -> alpha -> rho_GND (eqs. 10-13 and the curl of eq. B.3) for
-// the adjoint form: given rho_bar = dL/d rho_GND, produce dL/d alpha and dL/d Fp.
+// Adjoint form.  Reverse of the chain Fp -> alpha -> rho_GND (eqs. 10-13 and the curl of
+// eq. B.3): given rho_bar = dL/d rho_GND, produce dL/d alpha and dL/d Fp.  And the
+// sensitivity of the SSD density update (eqs. 8-9) to its parameters K and y_c.
 //
 //   k_gnd_adjoint   per voxel: alpha_c = R^T alpha R, segment densities rho = A^+ alpha_c / b,
 //                   u = sign(rho) * (system weights: 1 for the edge segment of each system,
@@ -77,6 +78,32 @@ __global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* ou
   out[i] = in[c * nv + zs * plane + (int64_t)ys * nx + xs];
 }
 
+// Sensitivity of the committed SSD densities (eqs. 8-9) to the similitude coefficient K and
+// the annihilation distance y_c at fixed slip increments: with S_a = sum_{b != a} (rho_SSD,b +
+// c_gnd rho_GND,b), 1/l_a = sqrt(S_a) / K and h_a = (1/b)(1/l_a - 2 y_c rho_SSD,a),
+//   d rho_a / dK = -|dg_a| sqrt(S_a) / (b K^2),   d rho_a / dy_c = -2 |dg_a| rho_SSD,a / b.
+// Rows a (K) and 12 + a (y_c) of out; zero without hardening (the densities do not evolve).
+__global__ void k_density_sensitivity(int64_t nv, const MatDev* mat, const double* rho_ssd, const double* rho_gnd,
+                                      const double* dg, double* out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const MatDev& M = *mat;
+  double rs[12], forest[12], tot = 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    rs[a] = rho_ssd[a * nv + v];
+    forest[a] = rs[a] + M.c_gnd * rho_gnd[a * nv + v];
+    tot += forest[a];
+  }
+  const double ib = 1.0 / M.burgers;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const double w = M.hardening ? fabs(dg[a * nv + v]) * ib : 0.0;
+    out[a * nv + v] = -w * sqrt(tot - forest[a]) / (M.K_sim * M.K_sim);
+    out[(12 + a) * nv + v] = -2.0 * w * rs[a];
+  }
+}
+
 }  // namespace
 
 void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const double* grainR,
@@ -84,6 +111,13 @@ void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const
   const int bs = 128;
   hipLaunchKernelGGL(k_gnd_adjoint, dim3((unsigned)((nv + bs - 1) / bs)), dim3(bs), 0, st, nv, nye, gid, grainR,
                      mat, rho_bar, alpha_bar);
+}
+
+void launch_density_sensitivity(int64_t nv, const MatDev* mat, const double* rho_ssd, const double* rho_gnd,
+                                const double* dg, double* out, hipStream_t st) {
+  const int bs = 128;
+  hipLaunchKernelGGL(k_density_sensitivity, dim3((unsigned)((nv + bs - 1) / bs)), dim3(bs), 0, st, nv, mat, rho_ssd,
+                     rho_gnd, dg, out);
 }
 
 void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st) {

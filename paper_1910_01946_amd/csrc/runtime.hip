@@ -1609,6 +1609,21 @@ int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const 
   });
 }
 
+int32_t rve_density_sensitivity(const rve_material* mat, int64_t nvox, const double* rho_ssd_n,
+                                const double* rho_gnd_n, const double* dg, double* out, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!mat || nvox < 1 || !rho_ssd_n || !rho_gnd_n || !dg || !out) throw Error(RVE_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    MatDev md = make_material(*mat);
+    DevBuf dmat;
+    upload(dmat, &md, sizeof(md));
+    launch_density_sensitivity(nvox, dmat.as<MatDev>(), rho_ssd_n, rho_gnd_n, dg, out, st);
+    check_launch("density sensitivity");
+    HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
 int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
                     const double* dc_target, double* out, void* stream) {
   return guarded([&]() -> int32_t {

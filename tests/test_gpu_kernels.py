@@ -103,6 +103,33 @@ def test_stress_sensitivity_matches_oracle_differences(lib, amp):
     assert (err < 2e-5).mean() >= 0.95
 
 
+@pytest.mark.parametrize("hard", [1, 0])
+def test_density_sensitivity_matches_oracle_differences(lib, hard):
+    """d rho_SSD / d(K, y_c) of the density update against central differences of the oracle's
+    update in the material parameters, at the oracle's converged slip increments (one system's
+    slip set to zero to cover the zero case)."""
+    import torch
+    mat = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=hard)
+    V = 1000
+    q, model, gid, F, Fp_n, rs, rg, dg0 = _points(V, 2e-3, 29, mat)
+    ref = cst.update(model, gid, F, Fp_n, rs, rg, 0.5, dg0)
+    dg = ref["dg"].copy()
+    dg[:, 5] = 0.0
+    S_ref = cst.density_param_sensitivity_fd(model, gid, Fp_n, rs, rg, dg)              # (V, 2, 12)
+    out = torch.full((24, V), float("nan"), dtype=torch.float64, device="cuda:0")
+    print(f"density sensitivity V={V} hardening={hard}", flush=True)
+    lib.density_sensitivity(mat, cuda(to_abi(rs)), cuda(to_abi(rg)), cuda(to_abi(dg)), out)
+    torch.cuda.synchronize()
+    S = out.cpu().numpy().reshape(2, 12, V).transpose(2, 0, 1)
+    if not hard:
+        assert not S.any() and not S_ref.any()
+        return
+    assert not S[:, :, 5].any()
+    for row in (0, 1):
+        assert np.abs(S_ref[:, row]).max() > 0
+        assert np.abs(S[:, row] - S_ref[:, row]).max() <= 1e-7 * np.abs(S_ref[:, row]).max()
+
+
 @pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 4), (10, 12, 6), (16, 16, 16), (64, 64, 64),
                                    (40, 48, 24), (96, 80, 6), (128, 128, 4)])
 @pytest.mark.parametrize("precision", [0, 1])
