@@ -366,3 +366,22 @@ def density_param_sensitivity_fd(model: MaterialModel, gid, Fp_n, rho_ssd_n, rho
             rho.append(_rho_ssd(PointData(m2, gid, Fp_n, rho_ssd_n, rho_gnd_n), dg))
         out[:, row, :] = (rho[0] - rho[1]) / (2.0 * step)
     return out
+
+
+def stress_fp_direction_fd(model: MaterialModel, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, D,
+                           step=1e-7):
+    """dP/dFp_n applied to directions D (V, 3, 3), by central differences of the converged
+    update in the start-of-increment plastic deformation gradient (each perturbed solve
+    warm-started from dg)."""
+    V = F.shape[0]
+    Fpm = np.repeat(Fp_n, 2, axis=0)
+    Dm = np.repeat(D, 2, axis=0)
+    Fpm[0::2] += step * Dm[0::2]
+    Fpm[1::2] -= step * Dm[1::2]
+    pd = PointData(model, np.repeat(gid, 2), Fpm, np.repeat(rho_ssd_n, 2, axis=0),
+                   np.repeat(rho_gnd_n, 2, axis=0))
+    F2 = np.repeat(F, 2, axis=0)
+    dgp, _, _ = solve_slip(pd, F2, dt, np.repeat(dg, 2, axis=0))
+    Ppm = stress(pd, F2, dgp)[0]
+    assert Ppm.shape[0] == 2 * V
+    return (Ppm[0::2] - Ppm[1::2]) / (2.0 * step)

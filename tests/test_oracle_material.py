@@ -135,3 +135,22 @@ def test_fd_density_parameter_sensitivity():
     mat0 = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=0)
     model0 = cst.MaterialModel(mat0, synth.shoemake_quaternions(synth.SplitMix64(3), 4))
     assert not cst.density_param_sensitivity_fd(model0, gid, Fp_n, rs, rg, out["dg"]).any()
+
+
+def test_fd_fp_sensitivity_step_consistency_and_tangent_identity():
+    """dP/dFp_n along random directions by central differences: the quotient has converged,
+    and it satisfies dP = -K : (Fe0 dFp_n) - P dFp_n^T Fp_n^-T with the oracle's own
+    difference tangent K (the slip increments depend on F and Fp_n only through
+    Fe0 = F Fp_n^-1, and P = Phi(Fe0) Fp_n^-T)."""
+    mat, model, gid, F, Fp_n, rs, rg = _setup(V=6, amp=2e-3)
+    dt = 0.5
+    out = cst.update(model, gid, F, Fp_n, rs, rg, dt, np.zeros_like(rs))
+    D = synth.random_field(31, (6, 3, 3))
+    S1 = cst.stress_fp_direction_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], D, step=1e-7)
+    S2 = cst.stress_fp_direction_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"], D, step=4e-7)
+    assert np.abs(S1 - S2).max() <= 1e-5 * np.abs(S1).max()
+    K = cst.tangent_fd(model, gid, F, Fp_n, rs, rg, dt, out["dg"])
+    Gn = np.linalg.inv(Fp_n)
+    Fe0 = F @ Gn
+    pred = -np.einsum("vijkl,vkl->vij", K, Fe0 @ D) - out["P"] @ np.swapaxes(D, 1, 2) @ np.swapaxes(Gn, 1, 2)
+    assert np.abs(pred - S1).max() <= 1e-5 * np.abs(S1).max()
