@@ -103,6 +103,37 @@ def test_stress_sensitivity_matches_oracle_differences(lib, amp):
     assert (err < 2e-5).mean() >= 0.95
 
 
+@pytest.mark.parametrize("amp", [3e-4, 2e-3])
+def test_fp_sensitivity_from_the_library_tangent_matches_oracle_differences(lib, amp):
+    """The sensitivity of P to the start-of-increment Fp follows from the tangent the library
+    returns: the slip increments depend on F and Fp_n only through Fe0 = F Fp_n^-1 and
+    P = Phi(Fe0) Fp_n^-T, so dP = -K : (Fe0 dFp_n) - P dFp_n^T Fp_n^-T.  With the library's K and
+    P, against central differences of the oracle's update in Fp_n along random directions."""
+    import torch
+    mat = synth.material("Cu", tau0=10e6, c_gnd=1.0, hardening=1)
+    V = 300
+    q, model, gid, F, Fp_n, rs, rg, dg0 = _points(V, amp, 37, mat)
+    dt = 0.5
+    ref = cst.update(model, gid, F, Fp_n, rs, rg, dt, dg0)
+    assert ref["converged"].all()
+    D = synth.random_field(38, (V, 3, 3))
+    S_ref = cst.stress_fp_direction_fd(model, gid, F, Fp_n, rs, rg, dt, ref["dg"], D)
+    t_dg = cuda(to_abi(dg0))
+    t_P = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    t_K = torch.zeros((81, V), dtype=torch.float64, device="cuda:0")
+    print(f"fp sensitivity V={V} amp={amp}", flush=True)
+    lib.constitutive_batch(mat, q, cuda(gid), cuda(to_abi(F)), cuda(to_abi(Fp_n)), cuda(to_abi(rs)),
+                           cuda(to_abi(rg)), dt, t_dg, t_P, t_K)
+    torch.cuda.synchronize()
+    P = from_abi(t_P.cpu().numpy())
+    K = t_K.cpu().numpy().T.reshape(V, 3, 3, 3, 3)
+    Gn = np.linalg.inv(Fp_n)
+    pred = -np.einsum("vijkl,vkl->vij", K, F @ Gn @ D) - P @ np.swapaxes(D, 1, 2) @ np.swapaxes(Gn, 1, 2)
+    err = np.abs(pred - S_ref).reshape(V, -1).max(axis=1) / np.abs(S_ref).reshape(V, -1).max(axis=1)
+    print("max relative difference", err.max(), flush=True)
+    assert err.max() < 2e-5
+
+
 @pytest.mark.parametrize("hard", [1, 0])
 def test_density_sensitivity_matches_oracle_differences(lib, hard):
     """d rho_SSD / d(K, y_c) of the density update against central differences of the oracle's
