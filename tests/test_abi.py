@@ -58,3 +58,26 @@ def test_gnd_adjoint_rejects_bad_arguments_before_any_device_call():
         rc = L.rve_gnd_adjoint(n, 0, h, nye, fake, ng, q, b, fake, None, out, None)
         assert rc == -1
         assert L.rve_last_error()
+
+
+def test_sensitivity_entry_points_reject_bad_arguments_before_any_device_call():
+    """rve_stress_sensitivity and rve_density_sensitivity check their arguments and the
+    material on the host: no GPU is needed to see the errors."""
+    from paper_1910_01946_amd import _lib, make_material
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    import synth
+    L = _lib.lib()
+    good = make_material(synth.material("Cu"))
+    bad = make_material(synth.material("Cu"))
+    bad.burgers = -1.0
+    q = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 0.0)
+    fake = ctypes.c_void_p(16)   # never dereferenced: every call below fails its host checks
+    m = ctypes.byref(good)
+    assert L.rve_stress_sensitivity(m, 1, q, 8, fake, fake, fake, fake, fake, 0.5, fake, None, None) == -1
+    assert L.rve_stress_sensitivity(m, 1, q, 8, fake, fake, fake, fake, fake, 0.0, fake, fake, None) == -1
+    assert L.rve_stress_sensitivity(m, 0, q, 8, fake, fake, fake, fake, fake, 0.5, fake, fake, None) == -1
+    assert L.rve_density_sensitivity(m, 8, fake, fake, None, fake, None) == -1
+    assert L.rve_density_sensitivity(m, 0, fake, fake, fake, fake, None) == -1
+    assert L.rve_density_sensitivity(ctypes.byref(bad), 8, fake, fake, fake, fake, None) == -1
+    assert L.rve_last_error()
