@@ -162,6 +162,74 @@ def test_adjoint_solve_matches_oracle_transposed_cg(lib):
     assert err < 1e-5
 
 
+def test_adjoint_gradient_of_the_macro_stress_matches_oracle_differences(lib):
+    """The adjoint pieces compose into the derivative of one increment's macroscopic stress.
+    With L = <P>_11 at the end of increment 3 (64-grain SGCP workload at 6^3, FP64) and
+    theta = c_GND: the perturbed equilibrium is G(K : dF + p) = 0 with dF in the range of G and
+    p = dP/dtheta at fixed F, and G is an orthogonal projection, so dL/dtheta = <e - lam, p>
+    with G(K^T : lam) = G(K^T : e), e the unit 11 field.  p comes from rve_stress_sensitivity
+    chained through eq. 7, lam from rve_adjoint_solve, K^T : e from rve_constitutive_batch.
+    Against central differences of the oracle's whole increment in c_GND (from the oracle's own
+    state after two increments; steps of 1e-2 and 1e-3 agree to 3e-7).  Without lam the value
+    is off by more than 1e-2, which the test checks."""
+    import copy
+    import dataclasses
+    import torch
+    rves, path = synth.workload("cu64", n_override=6, n_inc_override=50)
+    rve = rves[0]
+    mat = rve.material
+    V = rve.n_vox
+    o = solver.RVESolver(rve, newton_tol=1e-13, cg_tol=1e-12)
+    for k in (1, 2):
+        assert o.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)["converged"]
+
+    def L_of(c):
+        o2 = copy.deepcopy(o)
+        o2.model.mat = dataclasses.replace(o2.model.mat, c_gnd=c)
+        assert o2.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)["converged"]
+        return o2.macro()[0].reshape(-1)[0]
+
+    eps = 1e-3 * mat.c_gnd
+    dL_ref = (L_of(mat.c_gnd + eps) - L_of(mat.c_gnd - eps)) / (2 * eps)
+
+    h = lib.Homogenizer([rve], precision=lib.RVE_FP64, newton_tol=1e-13, cg_tol=1e-12, max_cg=4000)
+    for k in (1, 2):
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+    start = {n: h.field(n) for n in ("Fp", "rho_ssd", "rho_gnd")}
+    print("adjoint gradient: increment 3", flush=True)
+    h.step(path.F_bar[3], path.mask, path.P_bar[3], path.dt)
+    F_end, dg_end = h.field("F"), h.field("dg")
+    gid = cuda(rve.grain_of_voxel.reshape(-1))
+    args = [cuda(F_end), cuda(start["Fp"]), cuda(start["rho_ssd"]), cuda(start["rho_gnd"]), path.dt]
+    # K at the converged point (sample frame), then g = K^T : e, g_kl = K_11kl
+    t_dg = cuda(dg_end)
+    t_P = torch.zeros((9, V), dtype=torch.float64, device="cuda:0")
+    t_K = torch.zeros((81, V), dtype=torch.float64, device="cuda:0")
+    lib.constitutive_batch(mat, rve.quats, gid, *args, t_dg, t_P, t_K)
+    g = t_K[0:9].clone()
+    lam = torch.zeros_like(g)
+    it = h.adjoint_solve(g, path.mask, lam)
+    # p = dP/dc_GND at fixed F: dP/dtau_c times d tau_c,a / dc = (mu b)^2 sum_b q_ab rho_GND,b / (2 tau_c,a)
+    t_S = torch.zeros((108, V), dtype=torch.float64, device="cuda:0")
+    lib.stress_sensitivity(mat, rve.quats, gid, *args, cuda(dg_end), t_S)
+    torch.cuda.synchronize()
+    dPdtc = t_S.cpu().numpy().reshape(12, 9, V)
+    model = constitutive.MaterialModel(mat, rve.quats)
+    forest = start["rho_ssd"] + mat.c_gnd * start["rho_gnd"]
+    mub = model.mu * mat.burgers
+    tau_c = mub * np.sqrt(model.q @ forest)                          # (12, V)
+    dtc = mub * mub * (model.q @ start["rho_gnd"]) / (2.0 * tau_c)   # (12, V)
+    p = np.einsum("arv,av->rv", dPdtc, dtc)                          # (9, V)
+    lam_h = lam.cpu().numpy()
+    dL = float(np.mean(p[0] - np.sum(lam_h * p, axis=0)))
+    dL_local = float(np.mean(p[0]))
+    err = abs(dL - dL_ref) / abs(dL_ref)
+    print("adjoint gradient", dL, "oracle differences", dL_ref, "relative", err, "cg", it,
+          "without lam", dL_local, flush=True)
+    assert abs(dL_local - dL_ref) > 1e-2 * abs(dL_ref)
+    assert err < 1e-4
+
+
 def test_adjoint_solve_rejects_a_mixed_handle_and_an_unstepped_rve(lib):
     rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
     g = cuda(np.zeros((9, rves[0].n_vox)))
