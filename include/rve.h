@@ -254,10 +254,11 @@ int32_t rve_spectral_curl(const int32_t n[3], int32_t precision, double h, const
  * linearised (device, 9 x nvox, as written by rve_spectral_curl); the absolute values of the
  * per-system densities take the sign of each segment density (0 at a zero density).  gid
  * (device, nvox) holds grain ids in [0, n_grains); grain_quat (host, 4 x n_grains) the grain
- * orientations; burgers > 0 and h > 0 as for rve_spectral_curl.  All device buffers belong to
- * the caller and must not overlap.  The call allocates its own scratch, runs on stream (or the
- * null stream) and returns after the stream has finished.  RVE_EINVAL for a null pointer, a
- * non-positive h, burgers or n_grains. */
+ * orientations; burgers > 0 and h > 0 as for rve_spectral_curl; n (x, y, z sizes) and
+ * precision (RVE_FP64, or RVE_MIXED for FP32 spectra) as for rve_project.  All device buffers
+ * belong to the caller and must not overlap.  The call allocates its own scratch, runs on stream
+ * (or the null stream) and returns after the stream has finished.  RVE_EINVAL for a null
+ * pointer, a non-positive h, burgers or n_grains, or an unsupported grid size. */
 int32_t rve_gnd_adjoint(const int32_t n[3], int32_t precision, double h, const double* nye,
                         const int32_t* gid, int32_t n_grains, const double* grain_quat, double burgers,
                         const double* rho_bar, double* nye_bar, double* Fp_bar, void* stream);
