@@ -224,6 +224,16 @@ int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const 
                                const double* rho_ssd_n, const double* rho_gnd_n, double dt,
                                const double* dg, double* dPdtc, void* stream);
 
+/* Transposed application of the stress sensitivity, for the adjoint form: tau_c_bar[c * nvox +
+ * v] = sum_r w[r * nvox + v] dP_r / dtau_c,c (device out, 12 x nvox) for an adjoint field w
+ * (device, 9 x nvox, sample frame), without forming the 108 entries per voxel.  Other
+ * arguments and errors as for rve_stress_sensitivity. */
+int32_t rve_stress_sensitivity_vjp(const rve_material* mat, int32_t n_grains, const double* grain_quat,
+                                   int64_t nvox, const int32_t* gid, const double* F,
+                                   const double* Fp_n, const double* rho_ssd_n,
+                                   const double* rho_gnd_n, double dt, const double* dg,
+                                   const double* w, double* tau_c_bar, void* stream);
+
 /* Sensitivity of the SSD density update (eqs. 8-9) to its parameters, for the adjoint form:
  * out[a * nvox + v] = d rho_SSD,a / dK and out[(12 + a) * nvox + v] = d rho_SSD,a / dy_c
  * (device out, 24 x nvox, FP64) at fixed slip increments dg (device, 12 x nvox), from the

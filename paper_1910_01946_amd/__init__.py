@@ -16,7 +16,8 @@ from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rv
                    rve_options, rve_step_stats)
 
 __all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
-           "spectral_curl", "gnd_adjoint", "stress_sensitivity", "density_sensitivity",
+           "spectral_curl", "gnd_adjoint", "stress_sensitivity", "stress_sensitivity_vjp",
+           "density_sensitivity",
            "LibraryMissing", "RVEError", "lib"]
 
 FIELDS = {"F": (0, 9), "P": (1, 9), "Fp": (2, 9), "rho_ssd": (3, 12), "rho_gnd": (4, 12),
@@ -170,6 +171,16 @@ def stress_sensitivity(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, d
     check(lib().rve_stress_sensitivity(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
                                        _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
                                        _ptr(dg), _ptr(dPdtc), _stream(stream)))
+
+
+def stress_sensitivity_vjp(mat, quats, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, w, tau_c_bar, stream=None):
+    """tau_c_bar (12 x nvox) = sum_r w_r dP_r / dtau_c for an adjoint field w (9 x nvox), without
+    forming the full sensitivity (torch device tensors, component-major)."""
+    q = np.ascontiguousarray(quats, dtype=np.float64)
+    m = make_material(mat)
+    check(lib().rve_stress_sensitivity_vjp(C.byref(m), int(q.shape[0]), _dp(q), int(gid.numel()), _ptr(gid),
+                                           _ptr(F), _ptr(Fp_n), _ptr(rho_ssd_n), _ptr(rho_gnd_n), float(dt),
+                                           _ptr(dg), _ptr(w), _ptr(tau_c_bar), _stream(stream)))
 
 
 def density_sensitivity(mat, rho_ssd_n, rho_gnd_n, dg, out, stream=None):

@@ -102,6 +102,9 @@ def lib():
     L.rve_stress_sensitivity.argtypes = [P(rve_material), C.c_int32, dp, C.c_int64, vp, vp, vp, vp, vp, C.c_double,
                                          vp, vp, vp]
     L.rve_stress_sensitivity.restype = C.c_int32
+    L.rve_stress_sensitivity_vjp.argtypes = [P(rve_material), C.c_int32, dp, C.c_int64, vp, vp, vp, vp, vp,
+                                             C.c_double, vp, vp, vp, vp]
+    L.rve_stress_sensitivity_vjp.restype = C.c_int32
     L.rve_density_sensitivity.argtypes = [P(rve_material), C.c_int64, vp, vp, vp, vp, vp]
     L.rve_density_sensitivity.restype = C.c_int32
     L.rve_timing_start.argtypes = [vp, C.c_uint32]
@@ -119,7 +122,7 @@ EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress"
            "rve_state_bytes", "rve_save_state", "rve_load_state", "rve_destroy", "rve_last_error",
            "rve_constitutive_batch", "rve_project", "rve_spectral_curl", "rve_timing_start",
            "rve_timing_read", "rve_adjoint_solve", "rve_gnd_adjoint",
-           "rve_stress_sensitivity", "rve_density_sensitivity"]
+           "rve_stress_sensitivity", "rve_stress_sensitivity_vjp", "rve_density_sensitivity"]
 
 # kernel families of rve_timing_start / rve_timing_read
 KERNEL_FAMILIES = {"slip_fast": 0, "slip_slow": 1, "stress_tangent": 2, "cg_prep": 3, "plane_fwd": 4, "mid": 5,

@@ -13,8 +13,9 @@ void launch_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid, const
                         const MatDev* mat, const double* rho_bar, double* alpha_bar, hipStream_t st);
 
 // dPdtc (9 x 12 per voxel, sample frame, index (9c + r) * nvox + v) = dP_r / dtau_c,c at the
-// slip increments a.dg (constitutive.hip).
-void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, hipStream_t st);
+// slip increments a.dg (constitutive.hip); with w (9 x nvox) not null, dPdtc (12 x nvox) =
+// sum_r w_r dP_r / dtau_c,c instead.
+void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, const double* w, hipStream_t st);
 
 // out (24 x nv): d rho_SSD,a / dK (row a) and d rho_SSD,a / dy_c (row 12 + a) of eqs. 8-9 at
 // fixed slip increments dg (12 x nv), from the start-of-increment densities.

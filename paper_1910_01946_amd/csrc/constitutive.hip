@@ -459,8 +459,10 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
 // ddg = -J^{-1} e_c n g_c / tau_c,c (implicit function theorem), and the stress responds through
 // Fp alone: Z = sum_b ddg_b s_b (x) m_b, dEe = -sym(Ce Z A^{-1}), dS = C : dEe,
 // dP = -Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T (the F-direction terms of the
-// tangent vanish).  Output in the sample frame, dPdtc[(9c + r) * nvox + v] = dP_r / dtau_c,c.
-__global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, double* dPdtc) {
+// tangent vanish).  Output in the sample frame, dPdtc[(9c + r) * nvox + v] = dP_r / dtau_c,c;
+// or, with an adjoint field w (9 x nvox, sample frame), its transposed application
+// dPdtc[c * nvox + v] = sum_r w_r dP_r / dtau_c,c.
+__global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, double* dPdtc, const double* w) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
   if (v >= nv) return;
@@ -528,8 +530,15 @@ __global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, doubl
 #pragma unroll
     for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
     to_sample(Rg, dP, dPs);
+    if (w) {
+      double t = 0.0;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) dPdtc[(int64_t)(9 * c + r) * nv + v] = dPs[r];
+      for (int r = 0; r < 9; ++r) t += w[r * nv + v] * dPs[r];
+      dPdtc[(int64_t)c * nv + v] = t;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) dPdtc[(int64_t)(9 * c + r) * nv + v] = dPs[r];
+    }
   }
 }
 
@@ -623,10 +632,10 @@ void launch_constitutive(const ConstArgs& a, int ktype, hipStream_t st, LaunchTi
   }
 }
 
-void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, hipStream_t st) {
+void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, const double* w, hipStream_t st) {
   const int bs = 64;
   const int64_t nb = (a.nvox + bs - 1) / bs;
-  launch(k_stress_sensitivity, dim3((unsigned)nb), dim3(bs), 0u, st, a, dPdtc);
+  launch(k_stress_sensitivity, dim3((unsigned)nb), dim3(bs), 0u, st, a, dPdtc, w);
 }
 
 void launch_commit(const CommitArgs& a, hipStream_t st) {

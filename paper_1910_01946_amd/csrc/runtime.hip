@@ -1574,37 +1574,56 @@ int32_t rve_constitutive_batch(const rve_material* mat, int32_t n_grains, const 
   });
 }
 
+static void stress_sensitivity(const rve_material* mat, int32_t n_grains, const double* grain_quat, int64_t nvox,
+                               const int32_t* gid, const double* F, const double* Fp_n, const double* rho_ssd_n,
+                               const double* rho_gnd_n, double dt, const double* dg, const double* w, double* out,
+                               hipStream_t st) {
+  if (!mat || n_grains < 1 || !grain_quat || nvox < 1 || !gid || !F || !Fp_n || !rho_ssd_n || !rho_gnd_n || !dg ||
+      !out)
+    throw Error(RVE_EINVAL, "null argument");
+  if (!(std::isfinite(dt) && dt > 0)) throw Error(RVE_EINVAL, "dt must be > 0");
+  MatDev md = make_material(*mat);
+  std::vector<double> Rg(9 * (size_t)n_grains);
+  for (int g = 0; g < n_grains; ++g) quat_to_R(grain_quat + 4 * g, &Rg[9 * g]);
+  DevBuf dmat, dR;
+  upload(dmat, &md, sizeof(md));
+  upload(dR, Rg.data(), sizeof(double) * Rg.size());
+  ConstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nvox = nvox;
+  a.gid = gid;
+  a.grainR = dR.as<double>();
+  a.mat = dmat.as<MatDev>();
+  a.F = F;
+  a.Fp_n = Fp_n;
+  a.rho_ssd = rho_ssd_n;
+  a.rho_gnd = rho_gnd_n;
+  a.dg = const_cast<double*>(dg);   // read only
+  a.dt = dt;
+  launch_stress_sensitivity(a, out, w, st);
+  check_launch("stress sensitivity");
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
 int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const double* grain_quat, int64_t nvox,
                                const int32_t* gid, const double* F, const double* Fp_n, const double* rho_ssd_n,
                                const double* rho_gnd_n, double dt, const double* dg, double* dPdtc,
                                void* stream) {
   return guarded([&]() -> int32_t {
-    if (!mat || n_grains < 1 || !grain_quat || nvox < 1 || !gid || !F || !Fp_n || !rho_ssd_n || !rho_gnd_n || !dg ||
-        !dPdtc)
-      throw Error(RVE_EINVAL, "null argument");
-    if (!(std::isfinite(dt) && dt > 0)) throw Error(RVE_EINVAL, "dt must be > 0");
-    hipStream_t st = (hipStream_t)stream;
-    MatDev md = make_material(*mat);
-    std::vector<double> Rg(9 * (size_t)n_grains);
-    for (int g = 0; g < n_grains; ++g) quat_to_R(grain_quat + 4 * g, &Rg[9 * g]);
-    DevBuf dmat, dR;
-    upload(dmat, &md, sizeof(md));
-    upload(dR, Rg.data(), sizeof(double) * Rg.size());
-    ConstArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.nvox = nvox;
-    a.gid = gid;
-    a.grainR = dR.as<double>();
-    a.mat = dmat.as<MatDev>();
-    a.F = F;
-    a.Fp_n = Fp_n;
-    a.rho_ssd = rho_ssd_n;
-    a.rho_gnd = rho_gnd_n;
-    a.dg = const_cast<double*>(dg);   // read only
-    a.dt = dt;
-    launch_stress_sensitivity(a, dPdtc, st);
-    check_launch("stress sensitivity");
-    HIPCHECK(hipStreamSynchronize(st));
+    stress_sensitivity(mat, n_grains, grain_quat, nvox, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, nullptr, dPdtc,
+                       (hipStream_t)stream);
+    return RVE_OK;
+  });
+}
+
+int32_t rve_stress_sensitivity_vjp(const rve_material* mat, int32_t n_grains, const double* grain_quat,
+                                   int64_t nvox, const int32_t* gid, const double* F, const double* Fp_n,
+                                   const double* rho_ssd_n, const double* rho_gnd_n, double dt, const double* dg,
+                                   const double* w, double* tau_c_bar, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!w) throw Error(RVE_EINVAL, "null argument");
+    stress_sensitivity(mat, n_grains, grain_quat, nvox, gid, F, Fp_n, rho_ssd_n, rho_gnd_n, dt, dg, w, tau_c_bar,
+                       (hipStream_t)stream);
     return RVE_OK;
   });
 }

@@ -101,6 +101,23 @@ def test_stress_sensitivity_matches_oracle_differences(lib, amp):
     assert ref_max.max() > 0
     assert np.all(err < 2e-5 + 2.0 * est)
     assert (err < 2e-5).mean() >= 0.95
+    # transposed application to an adjoint field w: sum_r w_r dP_r/dtau_c, chained the same way,
+    # against the oracle's differences contracted with w
+    w = synth.random_field(24, (9, V))
+    tb = torch.full((12, V), float("nan"), dtype=torch.float64, device="cuda:0")
+    lib.stress_sensitivity_vjp(mat, q, cuda(gid), cuda(to_abi(F)), cuda(to_abi(Fp_n)), cuda(to_abi(rs)),
+                               cuda(to_abi(rg)), dt, cuda(to_abi(ref["dg"])), cuda(w), tb)
+    torch.cuda.synchronize()
+    g = np.einsum("av,vab->vb", tb.cpu().numpy(), dtc)
+    g_ref = np.einsum("rv,vrb->vb", w, S_ref.reshape(V, 9, 12))
+    g_fine = np.einsum("rv,vrb->vb", w, S_fine.reshape(V, 9, 12))
+    gmax = np.abs(g_ref).max(axis=1)
+    gnorm = gmax + 1e-3 * gmax.max()
+    gerr = np.abs(g - g_ref).max(axis=1) / gnorm
+    gest = np.abs(g_fine - g_ref).max(axis=1) / gnorm
+    print("transposed application: max relative difference", gerr.max(), flush=True)
+    assert np.all(gerr < 2e-5 + 2.0 * gest)
+    assert (gerr < 2e-5).mean() >= 0.95
 
 
 @pytest.mark.parametrize("amp", [3e-4, 2e-3])
