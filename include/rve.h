@@ -86,6 +86,14 @@ typedef struct {
   int32_t device;        /* HIP device ordinal                                               */
   void* stream;          /* hipStream_t to run on (for instance torch.cuda.current_stream());
                             NULL: the library's own stream                                   */
+  int32_t use_graph;     /* 1: the conjugate-gradient iterations of eq. 18 are issued as
+                            captured HIP graphs (one graph per chunk of iterations, captured
+                            once per RVE and replayed); 0: kernel by kernel.  Same results.  */
+  int32_t workers;       /* host threads that drive the RVEs of a handle concurrently, each
+                            RVE on its own stream; 0: the default (8, or RVE_WORKERS)         */
+  int32_t autotune;      /* 1: time the candidate z-pass tile widths of each grid size once
+                            per process at rve_create and keep the fastest (the tile width
+                            does not change any result); 0: the fixed rule                   */
 } rve_options;
 
 /* Per-RVE statistics of one increment. */
@@ -98,10 +106,15 @@ typedef struct {
   int32_t local_iters_max;   /* largest local Newton iteration count of any voxel               */
   double res_norm;           /* rms of the final projected residual G(P - P_bar), Pa           */
   double dF_norm;            /* rms of the last full Newton correction                          */
-  double voxel_iterations;   /* nvox * (residual_evals + cg_iters)                              */
+  double voxel_iterations;   /* nvox * (projected applies: residual evaluations + CG iterations)
+                                of the solve that produced the committed increment             */
   int32_t fp64_fallback;     /* RVE_MIXED: 1 if the FP32 attempt failed and the increment was
                                 solved with the FP64 spectral path                              */
-  int32_t pad;
+  int32_t continuation_stages; /* 0: solved directly; m: solved by load continuation in m stages
+                                after the direct attempt failed                                 */
+  double discarded_voxel_iterations; /* nvox * projected applies of failed attempts before the
+                                committed solve (counted in newton_iters, cg_iters and
+                                residual_evals, not in voxel_iterations)                       */
 } rve_step_stats;
 
 /* Create a handle holding n_rve RVEs (Section 2.2).  Per grain: rotation from the
@@ -109,7 +122,7 @@ typedef struct {
  * (Table 1 classes), segment matrix A and its minimum-norm inverse (eq. 13).
  * State: F = Fp = I, rho_SSD = rho0, rho_GND = 0.  opt may be NULL (defaults:
  * RVE_FP64, newton_tol 1e-10, cg_tol 1e-8, max_newton 40, max_cg 2000, max_backtrack 12,
- * device 0, own stream).  Errors: RVE_EINVAL (bad shape, grain id out of range,
+ * device 0, own stream, no graphs, 8 workers, no autotuning).  Errors: RVE_EINVAL (bad shape, grain id out of range,
  * non-finite or non-positive material constant, zero initial density), RVE_ENOMEM,
  * RVE_EDEVICE. */
 int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt, rve_handle* out);
@@ -151,14 +164,44 @@ int32_t rve_macro_stress(rve_handle h, int32_t rve, double* P_avg, double* F_avg
 int32_t rve_adjoint_solve(rve_handle h, int32_t rve, const uint8_t* mask, const double* g, double* lambda,
                           int32_t* cg_iters);
 
+/* Reverse pass of the last committed increment k of RVE rve, for the adjoint form: the
+ * implicit-function adjoint of the converged increment (Section 2.2, eqs. 16-18) through
+ * the transposed consistent tangent, and the reverse of the constitutive update (Section 2.1,
+ * eqs. 2-9 and 14) and of the GND chain of the start-of-increment state (eqs. 10-13, eq. 12
+ * with Appendix A).  For a loss L that depends on the increment's macroscopic stress <P>_k
+ * (eq. 15) and, through later increments, on its committed Fp_k and rho_SSD,k:
+ *   in:  dLdP (host, 9) = dL/d<P>_k (row-major);
+ *        Fp_bar (device, 9 x nvox) = dL/dFp_k, rho_bar (device, 12 x nvox) = dL/drho_SSD,k
+ *        (zeros for the last increment of a curve);
+ *   out: Fp_bar = dL/dFp_{k-1}, rho_bar = dL/drho_SSD,{k-1} (overwritten in place; the
+ *        GND densities of increment k-1 are folded into Fp_bar through the curl), and
+ *        theta_bar (host, 4) += the increment's contribution to dL/d(tau0, K, y_c, c_gnd):
+ *        tau0 the initial critical stress (uniform initial SSD density (tau0/(mu b))^2 /
+ *        sum_b q^{ab}, reached at k = 1, or tau_c itself when hardening is off), K of eq. 9,
+ *        y_c of eq. 8 and c_gnd of eqs. 7 and 9.
+ * Calling it for k = n, n-1, ..., 1 with the committed state of each increment restored
+ * (rve_save_state / rve_load_state checkpoints: a checkpoint holds the start-of-increment
+ * state too) accumulates the gradient of L with respect to the four parameters.
+ * The converged state is re-evaluated from the start-of-increment state (slip increments,
+ * stress and tangent in FP64) and the multiplier lam of G(K^T : lam) = G(g) is found by the
+ * forward conjugate-gradient kernels with the tangent read transposed (FP64 spectral path;
+ * mask as in rve_step_increment; cg_tol and max_cg of the handle).  Works on RVE_FP64 and
+ * RVE_MIXED handles (the reverse pass always runs in FP64).  cg_iters (host, may be NULL)
+ * receives the CG iteration count.  Device buffers belong to the caller and must not overlap.
+ * Errors: RVE_EINVAL (bad argument, planes that do not fit in LDS), RVE_ESTATE (no committed
+ * increment), RVE_ENOCONV (local Newton or CG failure); on error the outputs are undefined. */
+int32_t rve_adjoint_increment(rve_handle h, int32_t rve, const uint8_t* mask, const double* dLdP, double* Fp_bar,
+                              double* rho_bar, double* theta_bar, int32_t* cg_iters);
+
 /* Copy a committed field to a host buffer: which = 0 F (9), 1 P (9), 2 Fp (9),
  * 3 rho_SSD (12), 4 rho_GND (12), 5 Nye tensor (9), 6 slip increments of the last
  * increment (12).  Component-major, nvox per component. */
 int32_t rve_get_field(rve_handle h, int32_t rve, int32_t which, double* out);
 
 /* Save / restore the committed state of every RVE (F, Fp, rho_SSD, rho_GND, Nye, slip
- * increments, P and the previous increment's F) byte-exactly.  rve_state_bytes gives
- * the size of the host buffer. */
+ * increments, P, the previous increment's F, and the start-of-increment Fp, rho_SSD, rho_GND
+ * and time step of the last increment) byte-exactly.  rve_state_bytes gives the size of the
+ * host buffer. */
 int64_t rve_state_bytes(rve_handle h);
 int32_t rve_save_state(rve_handle h, void* buf);
 int32_t rve_load_state(rve_handle h, const void* buf);
@@ -226,8 +269,8 @@ int32_t rve_stress_sensitivity(const rve_material* mat, int32_t n_grains, const 
 
 /* Transposed application of the stress sensitivity, for the adjoint form: tau_c_bar[c * nvox +
  * v] = sum_r w[r * nvox + v] dP_r / dtau_c,c (device out, 12 x nvox) for an adjoint field w
- * (device, 9 x nvox, sample frame), without forming the 108 entries per voxel.  Other
- * arguments and errors as for rve_stress_sensitivity. */
+ * (device, 9 x nvox, sample frame), without forming the 108 entries per voxel.  w and
+ * tau_c_bar must not overlap.  Other arguments and errors as for rve_stress_sensitivity. */
 int32_t rve_stress_sensitivity_vjp(const rve_material* mat, int32_t n_grains, const double* grain_quat,
                                    int64_t nvox, const int32_t* gid, const double* F,
                                    const double* Fp_n, const double* rho_ssd_n,

@@ -44,7 +44,7 @@ class Homogenizer:
     """A set of RVEs advanced together through rve_step_increment."""
 
     def __init__(self, rves, precision=RVE_FP64, newton_tol=1e-10, cg_tol=1e-8, max_newton=40,
-                 max_cg=2000, max_backtrack=12, device=0, stream=None):
+                 max_cg=2000, max_backtrack=12, device=0, stream=None, use_graph=0, workers=0, autotune=0):
         L = lib()
         n = len(rves)
         self._keep = []
@@ -62,7 +62,8 @@ class Homogenizer:
             d.material = make_material(r.material)
         opt = rve_options(precision=precision, newton_tol=newton_tol, cg_tol=cg_tol, max_newton=max_newton,
                           max_cg=max_cg, max_backtrack=max_backtrack, device=device,
-                          stream=C.c_void_p(stream) if stream else None)
+                          stream=C.c_void_p(stream) if stream else None, use_graph=int(use_graph),
+                          workers=int(workers), autotune=int(autotune))
         h = C.c_void_p()
         check(L.rve_create(descs, n, C.byref(opt), C.byref(h)))
         self.h = h
@@ -132,6 +133,19 @@ class Homogenizer:
         n = C.c_int32(0)
         check(lib().rve_adjoint_solve(self.h, i, m.ctypes.data_as(C.POINTER(C.c_uint8)), _ptr(g), _ptr(lam),
                                       C.byref(n)))
+        return n.value
+
+    def adjoint_increment(self, mask, dLdP, Fp_bar, rho_bar, theta_bar, i=0):
+        """Reverse pass of the last committed increment of RVE i (rve_adjoint_increment).
+        dLdP: 9 host values; Fp_bar (9 x nvox), rho_bar (12 x nvox): device float64 tensors,
+        updated in place; theta_bar: host float64 array of 4, accumulated.  Returns the CG
+        iteration count of the multiplier solve."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(9))
+        w = np.ascontiguousarray(np.asarray(dLdP, dtype=np.float64).reshape(9))
+        assert theta_bar.dtype == np.float64 and theta_bar.flags.c_contiguous and theta_bar.size == 4
+        n = C.c_int32(0)
+        check(lib().rve_adjoint_increment(self.h, i, m.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(w), _ptr(Fp_bar),
+                                          _ptr(rho_bar), _dp(theta_bar), C.byref(n)))
         return n.value
 
     def save_state(self):

@@ -30,14 +30,16 @@ class rve_desc(C.Structure):
 class rve_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("newton_tol", C.c_double), ("cg_tol", C.c_double),
                 ("max_newton", C.c_int32), ("max_cg", C.c_int32), ("max_backtrack", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("use_graph", C.c_int32),
+                ("workers", C.c_int32), ("autotune", C.c_int32)]
 
 
 class rve_step_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32),
                 ("residual_evals", C.c_int32), ("line_search_cuts", C.c_int32),
                 ("local_iters_max", C.c_int32), ("res_norm", C.c_double), ("dF_norm", C.c_double),
-                ("voxel_iterations", C.c_double), ("fp64_fallback", C.c_int32), ("pad", C.c_int32)]
+                ("voxel_iterations", C.c_double), ("fp64_fallback", C.c_int32),
+                ("continuation_stages", C.c_int32), ("discarded_voxel_iterations", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +115,8 @@ def lib():
     L.rve_timing_read.restype = C.c_int32
     L.rve_adjoint_solve.argtypes = [vp, C.c_int32, P(C.c_uint8), vp, vp, P(C.c_int32)]
     L.rve_adjoint_solve.restype = C.c_int32
+    L.rve_adjoint_increment.argtypes = [vp, C.c_int32, P(C.c_uint8), dp, vp, vp, dp, P(C.c_int32)]
+    L.rve_adjoint_increment.restype = C.c_int32
     _lib = L
     return L
 
@@ -121,7 +125,7 @@ def lib():
 EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress", "rve_get_field",
            "rve_state_bytes", "rve_save_state", "rve_load_state", "rve_destroy", "rve_last_error",
            "rve_constitutive_batch", "rve_project", "rve_spectral_curl", "rve_timing_start",
-           "rve_timing_read", "rve_adjoint_solve", "rve_gnd_adjoint",
+           "rve_timing_read", "rve_adjoint_solve", "rve_adjoint_increment", "rve_gnd_adjoint",
            "rve_stress_sensitivity", "rve_stress_sensitivity_vjp", "rve_density_sensitivity"]
 
 # kernel families of rve_timing_start / rve_timing_read

@@ -66,7 +66,7 @@ __global__ void k_gnd_adjoint(int64_t nv, const double* nye, const int32_t* gid,
   for (int c = 0; c < 9; ++c) alpha_bar[c * nv + v] = q[c];
 }
 
-__global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* out) {
+__global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* out, int accumulate) {
   const int64_t plane = (int64_t)nx * ny, nv = plane * nz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 9 * nv) return;
@@ -75,7 +75,8 @@ __global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* ou
   const int64_t t = r - z * plane;
   const int y = (int)(t / nx), x = (int)(t - (int64_t)y * nx);
   const int zs = z == 0 ? nz - 1 : z - 1, ys = y == 0 ? ny - 1 : y - 1, xs = x == 0 ? nx - 1 : x - 1;
-  out[i] = in[c * nv + zs * plane + (int64_t)ys * nx + xs];
+  const double val = in[c * nv + zs * plane + (int64_t)ys * nx + xs];
+  out[i] = accumulate ? out[i] + val : val;
 }
 
 // Sensitivity of the committed SSD densities (eqs. 8-9) to the similitude coefficient K and
@@ -120,10 +121,11 @@ void launch_density_sensitivity(int64_t nv, const MatDev* mat, const double* rho
                      rho_gnd, dg, out);
 }
 
-void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st) {
+void launch_roll_back(int nx, int ny, int nz, const double* in, double* out, hipStream_t st, bool accumulate) {
   const int bs = 256;
   const int64_t n = 9 * (int64_t)nx * ny * nz;
-  hipLaunchKernelGGL(k_roll_back, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, nx, ny, nz, in, out);
+  hipLaunchKernelGGL(k_roll_back, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, nx, ny, nz, in, out,
+                     accumulate ? 1 : 0);
 }
 
 }  // namespace rve

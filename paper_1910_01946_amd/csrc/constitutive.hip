@@ -462,7 +462,8 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
 // tangent vanish).  Output in the sample frame, dPdtc[(9c + r) * nvox + v] = dP_r / dtau_c,c;
 // or, with an adjoint field w (9 x nvox, sample frame), its transposed application
 // dPdtc[c * nvox + v] = sum_r w_r dP_r / dtau_c,c.
-__global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, double* dPdtc, const double* w) {
+__global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, double* __restrict__ dPdtc,
+                                                             const double* __restrict__ w) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
   if (v >= nv) return;
@@ -488,6 +489,10 @@ __global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, doubl
   mm3(k.Ainv, SGt, Q);             // A^{-1} S G^T
   mmt3(k.S, k.Ainv, AtS);          // S A^{-T}
   mm3(k.Fe, AtS, W);               // Fe S A^{-T}
+  // the adjoint field is read once, before any output is written
+  double wv[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) wv[r] = w ? w[r * nv + v] : 0.0;
 #pragma unroll 1
   for (int c = 0; c < 12; ++c) {
     double x[12];
@@ -533,11 +538,239 @@ __global__ void __launch_bounds__(64) k_stress_sensitivity(ConstArgs args, doubl
     if (w) {
       double t = 0.0;
 #pragma unroll
-      for (int r = 0; r < 9; ++r) t += w[r * nv + v] * dPs[r];
+      for (int r = 0; r < 9; ++r) t += wv[r] * dPs[r];
       dPdtc[(int64_t)c * nv + v] = t;
     } else {
 #pragma unroll
       for (int r = 0; r < 9; ++r) dPdtc[(int64_t)(9 * c + r) * nv + v] = dPs[r];
+    }
+  }
+}
+
+// Reverse of the constitutive update of one increment, for the adjoint form (eqs. 2-9,
+// 14, differentiated).  At the converged slip increments dg of an increment with
+// start-of-increment state (Fp_n, rho_SSD,n, rho_GND,n), the outputs P (eq. 14), Fp (eq. 2)
+// and rho_SSD (eq. 8) depend on F and on that state directly and through the root dg of the
+// flow rule (eq. 6).  Given output weights P_bar, Fp_bar, rho_bar, the kernel forms the
+// derivative of L = <P_bar, P> + <Fp_bar, Fp> + <rho_bar, rho_SSD> with respect to
+//   mode 0: F (the right-hand side g of the adjoint equilibrium), and
+//   mode 1: Fp_n, rho_SSD,n, rho_GND,n and the parameters (K, y_c, c_gnd; tau0 when
+//           hardening is off), all at fixed F.
+// Both modes run the same reverse sweep in the crystal frame:
+//   1. at fixed dg, back through P = Fe S G^T, S = C : (Fe^T Fe - I)/2, Fe = Fe0 A^-1,
+//      G = Gn A^-1, Fp = A Fp_n, A = I + sum dg_a s_a (x) m_a, rho_SSD = rho_n + h |dg|;
+//      this gives dg_bar and the direct bars of Fe0 = F Gn and Gn = Fp_n^-1;
+//   2. implicit function: mu = J^-T dg_bar with J = dR/d(dg) (the local Newton's Jacobian);
+//      R_a = dg_a - g_a(tau_a, tau_c,a) adds tau_bar = D mu (D_a = dg_a/dtau_a) back through
+//      tau_a = s_a . S m_a at fixed dg, and tau_c_bar_a = -mu_a n g_a / tau_c,a;
+//   3. Fe0 = F Gn, Gn = Fp_n^-1 give F_bar and Fp_n_bar; tau_c (eq. 7) and h (eqs. 8-9) give
+//      the density and parameter bars.
+// The absolute value |dg| takes the derivative sgn(dg) with sgn(0) = 0.
+__device__ __forceinline__ void lu12_solve_t(const double J[12][12], double* x) {
+  // J = L U (unit L below the diagonal, U on and above it); J^T x = b: U^T y = b, L^T x = y
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+#pragma unroll
+    for (int c = 0; c < r; ++c) x[r] -= J[c][r] * x[c];
+    x[r] /= J[r][r];
+  }
+#pragma unroll
+  for (int r = 11; r >= 0; --r)
+#pragma unroll
+    for (int c = r + 1; c < 12; ++c) x[r] -= J[c][r] * x[c];
+}
+
+// Fe_bar += Fe (C : sym(S_bar)): reverse of S = C : (Fe^T Fe - I) / 2
+__device__ __forceinline__ void rev_elastic_stress(const Point& p, const double* Fe, const double* Sb, double* Feb) {
+  double Ss[9], Eb[9], t[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Ss[3 * i + j] = 0.5 * (Sb[3 * i + j] + Sb[3 * j + i]);
+  cubic_stress(p, Ss, Eb);
+  mm3(Fe, Eb, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Feb[i] += t[i];
+}
+
+__global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, AdjointLocalArgs b) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = args.nvox;
+  double th[4] = {0.0, 0.0, 0.0, 0.0};  // K, y_c, c_gnd, tau0 (mode 1)
+  if (v < nv) {
+    const MatDev& M = *args.mat;
+    double Rg[9];
+    Point p;
+    ConstArgs a2 = args;
+    a2.F_out = nullptr;
+    setup_point(a2, M, v, nv, nullptr, Rg, p);
+    double Fs[9], Fc[9], Fpn_s[9], Fpn[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      Fs[i] = args.F[i * nv + v];
+      Fpn_s[i] = args.Fp_n[i * nv + v];
+    }
+    to_crystal(Rg, Fs, Fc);
+    to_crystal(Rg, Fpn_s, Fpn);
+    double dg[12];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
+    Kin k;
+    double R[12], D[12];
+    residual(p, M.n_exp, dg, k, R, D);
+    // output weights in the crystal frame (read before any output is written: in-place safe)
+    double Pb[9], Fpb[9], rb[12], t[9], t2[9];
+    {
+      double ws[9], fs[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        ws[i] = b.wP[i] - (b.lam ? b.lam[i * nv + v] : 0.0);
+        fs[i] = b.Fp_bar ? b.Fp_bar[i * nv + v] : 0.0;
+      }
+      to_crystal(Rg, ws, Pb);
+      to_crystal(Rg, fs, Fpb);
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) rb[a] = b.rho_bar ? b.rho_bar[a * nv + v] : 0.0;
+    double G[9];
+    mm3(p.Gn, k.Ainv, G);  // Fp^-1
+    // ---- 1. reverse sweep at fixed dg ----
+    double Feb[9], Sb[9], Gb[9];
+    mm3(Pb, G, t);
+    mm3(t, k.S, Feb);      // Fe_bar = P_bar G S
+    mtm3(k.Fe, Pb, t);
+    mm3(t, G, Sb);         // S_bar = Fe^T P_bar G
+    mtm3(Pb, k.Fe, t);
+    mm3(t, k.S, Gb);       // G_bar = P_bar^T Fe S
+    rev_elastic_stress(p, k.Fe, Sb, Feb);
+    double Fe0b[9], Aib[9], Gnb[9], Ab[9];
+    mmt3(Feb, k.Ainv, Fe0b);  // Fe = Fe0 A^-1
+    mtm3(p.Fe0, Feb, Aib);
+    mmt3(Gb, k.Ainv, Gnb);    // G = Gn A^-1
+    mtm3(p.Gn, Gb, t);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Aib[i] += t[i];
+    mtm3(k.Ainv, Aib, t);     // A_bar = -A^-T Ai_bar A^-T
+    mmt3(t, k.Ainv, Ab);
+    mmt3(Fpb, Fpn, t);        // Fp = A Fp_n
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Ab[i] = t[i] - Ab[i];
+    double Fpnb[9];
+    mtm3(k.A, Fpb, Fpnb);
+    // densities: rho_SSD = rho_n + h |dg| with h from the start-of-increment forest
+    double rn[12], rg[12], f[12], sq[12], h[12], tot = 0.0;
+    const bool hard = M.hardening != 0;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      rn[a] = args.rho_ssd[a * nv + v];
+      rg[a] = args.rho_gnd[a * nv + v];
+      f[a] = rn[a] + M.c_gnd * rg[a];
+      tot += f[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      sq[a] = sqrt(tot - f[a]);
+      h[a] = hard ? (1.0 / M.burgers) * (sq[a] / M.K_sim - 2.0 * M.y_c * rn[a]) : 0.0;
+    }
+    double mu[12];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s += kSlipS[a][i] * Ab[3 * i + j] * kSlipM[a][j];
+      const double sg = dg[a] > 0.0 ? 1.0 : (dg[a] < 0.0 ? -1.0 : 0.0);
+      mu[a] = s + rb[a] * h[a] * sg;
+    }
+    // ---- 2. implicit function of the flow rule ----
+    {
+      double J[12][12];
+      jacobian(p, k, D, J);
+      lu12(J);
+      lu12_solve_t(J, mu);
+    }
+    {
+      double Sb2[9], Feb2[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Sb2[i] = 0.0, Feb2[i] = 0.0;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        const double tb = D[a] * mu[a];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Sb2[3 * i + j] += tb * kSlipS[a][i] * kSlipM[a][j];
+      }
+      rev_elastic_stress(p, k.Fe, Sb2, Feb2);
+      mmt3(Feb2, k.Ainv, t);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Fe0b[i] += t[i];
+    }
+    // ---- 3. inputs ----
+    if (b.mode == 0) {
+      double Fb[9];
+      mmt3(Fe0b, p.Gn, Fb);  // Fe0 = F Gn
+      to_sample(Rg, Fb, t);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) b.g[i * nv + v] = t[i];
+    } else {
+      mtm3(Fc, Fe0b, t);     // Gn_bar += F^T Fe0_bar
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Gnb[i] += t[i];
+      mtm3(p.Gn, Gnb, t);    // Gn = Fp_n^-1: Fp_n_bar -= Gn^T Gn_bar Gn^T
+      mmt3(t, p.Gn, t2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Fpnb[i] -= t2[i];
+      to_sample(Rg, Fpnb, t);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) b.Fp_bar_out[i * nv + v] = t[i];
+      double tcb[12];
+#pragma unroll
+      for (int a = 0; a < 12; ++a) tcb[a] = -mu[a] * M.n_exp * (dg[a] - R[a]) / p.tc[a];
+      double rnb[12], fb[12];
+      if (hard) {
+        double wsum = 0.0, wk[12];
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          const double w = rb[a] * fabs(dg[a]);
+          wk[a] = w / (2.0 * M.burgers * M.K_sim * sq[a]);
+          wsum += wk[a];
+          rnb[a] = rb[a] - w * 2.0 * M.y_c / M.burgers;
+          th[0] -= w * sq[a] / (M.burgers * M.K_sim * M.K_sim);
+          th[1] -= w * 2.0 * rn[a] / M.burgers;
+        }
+        const double mb2 = M.mu * M.burgers * M.mu * M.burgers;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          double s = wsum - wk[c];
+#pragma unroll
+          for (int a = 0; a < 12; ++a) s += tcb[a] * mb2 * M.q[12 * a + c] / (2.0 * p.tc[a]);
+          fb[c] = s;
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          rnb[c] += fb[c];
+          th[2] += fb[c] * rg[c];
+          b.rho_bar_out[c * nv + v] = rnb[c];
+          b.rho_gnd_bar[c * nv + v] = M.c_gnd * fb[c];
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          th[3] += tcb[a];
+          b.rho_bar_out[a * nv + v] = rb[a];
+          b.rho_gnd_bar[a * nv + v] = 0.0;
+        }
+      }
+    }
+  }
+  if (b.mode == 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double s = th[i];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+      if (threadIdx.x == 0) b.theta_partial[4 * blockIdx.x + i] = s;
     }
   }
 }
@@ -636,6 +869,13 @@ void launch_stress_sensitivity(const ConstArgs& a, double* dPdtc, const double* 
   const int bs = 64;
   const int64_t nb = (a.nvox + bs - 1) / bs;
   launch(k_stress_sensitivity, dim3((unsigned)nb), dim3(bs), 0u, st, a, dPdtc, w);
+}
+
+int launch_constitutive_adjoint(const ConstArgs& a, const AdjointLocalArgs& b, hipStream_t st) {
+  const int bs = 64;
+  const int64_t nb = (a.nvox + bs - 1) / bs;
+  launch(k_constitutive_adjoint, dim3((unsigned)nb), dim3(bs), 0u, st, a, b);
+  return (int)nb;
 }
 
 void launch_commit(const CommitArgs& a, hipStream_t st) {

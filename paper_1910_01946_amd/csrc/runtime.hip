@@ -47,6 +47,42 @@ static void check_launch(const char* what) {
   if (e != hipSuccess) throw Error(RVE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Settings read from the environment once per process (std::call_once), before any
+// worker thread exists, so that no thread races on their first read:
+//   RVE_TRACE=1      one line per Newton iteration on stderr;
+//   RVE_PREDICT=0    start every local solve from the previous slip increments instead of
+//                    their first-order prediction (same converged result);
+//   RVE_PLANE=0      the three-pass (x, y, z) spectral kernels even where the plane kernels
+//                    fit (both are kept and tested);
+//   RVE_TANGENT16=0  the mixed form's tangent copy in FP32 instead of scaled FP16;
+//   RVE_TZ=t         cap on the z-pass tile width;
+//   RVE_WORKERS=w    host threads driving RVEs concurrently (default 8).
+struct Settings {
+  bool trace = false, predict = true, plane = true, tangent16 = true;
+  int tz_cap = 0, workers = 8;
+};
+static const Settings& settings() {
+  static Settings s;
+  static std::once_flag once;
+  std::call_once(once, []() {
+    auto env = [](const char* name) -> const char* {
+      const char* e = std::getenv(name);
+      return (e && e[0]) ? e : nullptr;
+    };
+    if (const char* e = env("RVE_TRACE")) s.trace = e[0] != '0';
+    if (const char* e = env("RVE_PREDICT")) s.predict = e[0] != '0';
+    if (const char* e = env("RVE_PLANE")) s.plane = e[0] != '0';
+    if (const char* e = env("RVE_TANGENT16")) s.tangent16 = e[0] != '0';
+    if (const char* e = env("RVE_TZ")) s.tz_cap = std::max(1, std::atoi(e));
+    if (const char* e = env("RVE_WORKERS")) s.workers = std::max(1, std::atoi(e));
+  });
+  return s;
+}
+static bool trace_on() { return settings().trace; }
+static bool prediction_enabled() { return settings().predict; }
+static bool plane_enabled() { return settings().plane; }
+static bool tangent16_enabled() { return settings().tangent16; }
+
 // ------------------------------------------------------------------------------------
 // host-side tables (independent of any other implementation)
 // ------------------------------------------------------------------------------------
@@ -248,10 +284,10 @@ struct Plan {
   DevBuf tw[3], E[3];
 };
 
-static void build_plan(Plan& P, const int n[3], bool fp32) {
+// Sizes, radix plans, tile widths and divisors of a grid (no tables, nothing allocated).
+static void plan_geometry(GridPlan& g, const int n[3], int tz_choice = 0) {
   for (int d = 0; d < 3; ++d)
     if (n[d] < 1 || n[d] > 256) throw Error(RVE_EINVAL, "grid sizes must lie in 1..256");
-  GridPlan& g = P.g;
   g.nx = n[0];
   g.ny = n[1];
   g.nz = n[2];
@@ -270,11 +306,33 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
   // kx columns per z-pass block: nz * tz <= 256, i.e. at most 9 points per thread of a
   // 256-thread block (the z-pass transform is compiled for that bound)
   g.tz = std::max(1, std::min(g.nxh, 256 / g.nz));
-  if (const char* e = std::getenv("RVE_TZ")) g.tz = std::max(1, std::min(g.tz, std::atoi(e)));
+  if (tz_choice > 0) g.tz = std::min(g.tz, tz_choice);
+  if (settings().tz_cap > 0) g.tz = std::min(g.tz, settings().tz_cap);
   g.fnx = make_fastdiv(g.nx);
   g.fnxh = make_fastdiv(g.nxh);
   g.fnz = make_fastdiv(g.nz);
   g.ftz = make_fastdiv(g.tz);
+}
+
+// Tile widths chosen by the autotuner, per (grid, spectral precision), for the whole process.
+struct TuneKey {
+  int n0, n1, n2, fp32;
+  bool operator==(const TuneKey& o) const { return n0 == o.n0 && n1 == o.n1 && n2 == o.n2 && fp32 == o.fp32; }
+};
+static std::mutex g_tune_mu;
+static std::vector<std::pair<TuneKey, int>> g_tuned_tz;
+
+static int tuned_tz(const int n[3], bool fp32) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const TuneKey k{n[0], n[1], n[2], fp32 ? 1 : 0};
+  for (const auto& e : g_tuned_tz)
+    if (e.first == k) return e.second;
+  return 0;
+}
+
+static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false) {
+  GridPlan& g = P.g;
+  plan_geometry(g, n, autotune ? tuned_tz(n, fp32) : 0);
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
     const int m = n[d];
@@ -313,26 +371,6 @@ static void build_plan(Plan& P, const int n[3], bool fp32) {
 
 static size_t tsize(bool fp32) { return fp32 ? 4 : 8; }
 
-// RVE_TRACE=1 in the environment prints one line per Newton iteration to stderr.
-static bool trace_on() {
-  static int on = -1;
-  if (on < 0) {
-    const char* e = std::getenv("RVE_TRACE");
-    on = (e && e[0] && e[0] != '0') ? 1 : 0;
-  }
-  return on == 1;
-}
-
-// RVE_PREDICT=0 in the environment starts every local solve from the previous slip
-// increments instead of their first-order prediction (same converged result).
-static bool prediction_enabled() {
-  static int on = -1;
-  if (on < 0) {
-    const char* e = std::getenv("RVE_PREDICT");
-    on = (e && e[0] == '0') ? 0 : 1;
-  }
-  return on == 1;
-}
 
 // ------------------------------------------------------------------------------------
 // one RVE on the device
@@ -346,20 +384,17 @@ struct Work {
   bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
   bool k16 = false;    // FP32 work set with the plane path: tangent copy as scaled FP16 pairs
   bool k_ready = false;  // K holds the tangent of the last constitutive evaluation with tangent
+  // captured CG chunks (one HIP graph each), by [tangent transposed][CG unknown xa or xb]
+  hipGraphExec_t cg_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  Work() = default;
+  Work(const Work&) = delete;
+  Work& operator=(const Work&) = delete;
+  ~Work() {
+    for (auto& row : cg_graph)
+      for (hipGraphExec_t& e : row)
+        if (e) (void)hipGraphExecDestroy(e);
+  }
 };
-
-// RVE_PLANE=0 in the environment selects the three-pass (x, y, z) spectral kernels even
-// where the plane kernels fit (both are kept and tested).
-static bool plane_enabled() {
-  const char* e = std::getenv("RVE_PLANE");
-  return !(e && e[0] == '0');
-}
-
-// RVE_TANGENT16=0 keeps the mixed form's tangent copy in FP32.
-static bool tangent16_enabled() {
-  const char* e = std::getenv("RVE_TANGENT16");
-  return !(e && e[0] == '0');
-}
 
 // Times the launches of the families in mask with HIP events that the kernel dispatch
 // itself records at the kernel's start and end (on the launching stream), and accumulates
@@ -471,6 +506,11 @@ struct RVE {
   DevBuf d_mat, d_gid, d_R;
   // committed state
   DevBuf F, F_prev, Fp, rho_ssd, rho_gnd, nye, dg, P;
+  // start-of-increment state of the last committed increment (for its reverse pass)
+  DevBuf Fp_prev, rho_ssd_prev, rho_gnd_prev;
+  double dt_last = 0.0;
+  // work buffers of the reverse pass (allocated on first use)
+  DevBuf adj_a9, adj_b9, adj_rgb, adj_theta;
   // work
   DevBuf F_work, F_try, P_work, dg_saved, cg, partial, blk;
   DevBuf dgdF;  // FP32 slip sensitivity d(dg)/dF_c, 108 x nvox, written with the tangent
@@ -483,6 +523,7 @@ struct RVE {
   Plan proj_plan;                 // FP64 projection of the Newton correction (mixed form)
   DevBuf proj_spec, x64;
   bool proj_ready = false;
+  bool autotune = false;          // plans take the autotuned z-pass tile width
   LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
     if (host_cg) (void)hipHostFree(host_cg);
@@ -501,6 +542,8 @@ struct Ctx {
   int device = 0;
   bool fp32 = false;
   int workers = 8;               // host threads driving RVEs concurrently
+  bool use_graph = false;        // CG chunks as captured HIP graphs
+  bool autotune = false;         // autotuned z-pass tile widths
   rve_options opt;
   hipStream_t stream = nullptr;  // caller's stream (optional)
   bool own_stream = false;
@@ -516,7 +559,7 @@ static Work& work(RVE& R, bool fp32) {
   Work& w = R.w[fp32 ? 1 : 0];
   if (!w.ready) {
     w.fp32 = fp32;
-    build_plan(w.plan, R.n, fp32);
+    build_plan(w.plan, R.n, fp32, R.autotune);
     const int64_t nv = R.nvox;
     const size_t ts = tsize(fp32);
     // grouped layout: G groups of W entries per voxel (see tangent_index)
@@ -540,6 +583,7 @@ static Work& work(RVE& R, bool fp32) {
 
 static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   for (int i = 0; i < 3; ++i) R.n[i] = d.n[i];
+  R.autotune = C.autotune;
   R.nvox = (int64_t)d.n[0] * d.n[1] * d.n[2];
   if (!(std::isfinite(d.voxel_size) && d.voxel_size > 0)) throw Error(RVE_EINVAL, "voxel_size must be > 0");
   R.h = d.voxel_size;
@@ -577,6 +621,10 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   HIPCHECK(hipMemset(R.dg.p, 0, f12));
   R.P.alloc(f9);
   HIPCHECK(hipMemset(R.P.p, 0, f9));
+  upload(R.Fp_prev, eye.data(), f9);
+  upload(R.rho_ssd_prev, rho.data(), f12);
+  R.rho_gnd_prev.alloc(f12);
+  HIPCHECK(hipMemset(R.rho_gnd_prev.p, 0, f12));
   R.F_work.alloc(f9);
   R.F_try.alloc(f9);
   R.P_work.alloc(f9);
@@ -706,7 +754,7 @@ static void project_field(const GridPlan& g, bool fp32, bool plane, void* spec, 
 static const double* newton_correction(RVE& R, Work& w, const void* x, const double* keep) {
   if (!w.fp32) return static_cast<const double*>(x);
   if (!R.proj_ready) {
-    build_plan(R.proj_plan, R.n, false);
+    build_plan(R.proj_plan, R.n, false, R.autotune);
     R.proj_spec.alloc(tsize(false) * 2 * 9 * R.proj_plan.g.nspec);
     R.x64.alloc(sizeof(double) * 9 * (size_t)R.nvox);
     R.proj_ready = true;
@@ -798,7 +846,7 @@ static double run_residual(Ctx& C, RVE& R, Work& w, const double* P64, const dou
 
 // conjugate gradients on G(K : x) = r (x, r, p set by run_residual); returns iterations
 static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int& done_code,
-                  bool transpose = false) {
+                  bool transpose = false, double rr_floor = 0.0) {
   const GridPlan& g = w.plan.g;
   CGState* cg = R.cg.as<CGState>();
   double* part = R.partial.as<double>();
@@ -811,6 +859,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
     s.it_best = 0;
     s.done = (s.rr0 > 0.0 && C.opt.max_cg > 0) ? 0 : 1;
     s.tol2 = C.opt.cg_tol * C.opt.cg_tol;
+    s.rr_floor = rr_floor;
     s.max_iter = C.opt.max_cg;
     *R.host_cg = s;
     HIPCHECK(hipMemcpyAsync(cg, R.host_cg, sizeof(CGState), hipMemcpyHostToDevice, R.stream));
@@ -914,6 +963,29 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
     HIPCHECK(hipMemcpyAsync(&R.host_poll[s], cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
     HIPCHECK(hipEventRecord(R.poll_ev[s], R.stream));
   };
+  // Chunks after the first differ from each other in nothing but the iteration tag (the
+  // first iteration of a solve is the only special one), so with use_graph they are captured
+  // once as a HIP graph per (transposed tangent, CG unknown) and replayed.
+  const bool graph = C.use_graph && w.plane && !R.tm();
+  auto issue_later_chunk = [&]() {
+    if (!graph) {
+      issue_chunk();
+      return;
+    }
+    hipGraphExec_t& ge = w.cg_graph[transpose ? 1 : 0][x == w.xa.p ? 0 : 1];
+    if (!ge) {
+      hipGraph_t gr = nullptr;
+      HIPCHECK(hipStreamBeginCapture(R.stream, hipStreamCaptureModeThreadLocal));
+      issue_chunk();  // recorded, not run
+      HIPCHECK(hipStreamEndCapture(R.stream, &gr));
+      const hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      HIPCHECK(e);
+    } else {
+      issued += chunk;
+    }
+    HIPCHECK(hipGraphLaunch(ge, R.stream));
+  };
   if (!R.host_cg->done) {
     // the stop flag of chunk c - 1 is read while chunk c is already queued, so the GPU
     // never waits for the host; once the flag is set, the kernels of the chunk in flight
@@ -921,7 +993,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
     issue_chunk();
     snapshot(0);
     for (int c = 1;; ++c) {
-      issue_chunk();
+      issue_later_chunk();
       snapshot(c & 1);
       HIPCHECK(hipEventSynchronize(R.poll_ev[(c - 1) & 1]));
       if (R.host_poll[(c - 1) & 1].done) break;
@@ -1007,6 +1079,27 @@ static void run_nye(Ctx& C, RVE& R, Work& w) {
   check_launch("nye");
 }
 
+// Curl (eq. 12 with the rotated-scheme derivative) of a 9-component FP64 field on the FP64
+// plane path: src is Fp (minus_identity: the curl of Fp - I) or a plain field.
+static void curl_plane64(const GridPlan& g, void* spec, const double* src, bool minus_identity, double inv_h,
+                         double* out, hipStream_t st) {
+  PlaneArgs pa{minus_identity ? PF_FPI : PF_F64, src, spec};
+  launch_plane_fwd(g, false, pa, nullptr, st);
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.op = MID_CURL;
+  m.spec = spec;
+  m.inv_n = 1.0 / (double)g.nvox;
+  m.inv_h = inv_h;
+  launch_mid(g, false, m, st);
+  PlaneInvArgs pi;
+  std::memset(&pi, 0, sizeof(pi));
+  pi.mode = PI_OUT64;
+  pi.spec = spec;
+  pi.out64 = out;
+  launch_plane_inv(g, false, pi, st);
+}
+
 // ------------------------------------------------------------------------------------
 // one increment of one RVE (Section 2.2)
 // ------------------------------------------------------------------------------------
@@ -1014,10 +1107,27 @@ static void run_nye(Ctx& C, RVE& R, Work& w) {
 // of the deformation-controlled components fixed by that field.  Returns RVE_OK when the
 // applied correction falls below newton_tol; F_work then holds the solution and P_work,
 // dg the matching stress and slip increments.
+// Rounding floor of the mixed form's FP32 residual.  The projected residual G(P - P_bar) is
+// formed from a stress field of magnitude rms(P) with FP32 transforms, so its rms carries a
+// rounding error of about u32 rms(P) (u32 = 2^-24; measured: Newton stagnates at 1 to 2 times
+// that value).  A conjugate-gradient solve stops once its residual is within kCgFloor of that
+// floor (a smaller one is not resolved), and a Newton correction below newton_tol whose full
+// step brings the residual within kNewtonFloor of it ends the increment even when CG did not
+// converge: at the floor the right-hand side is rounding noise, to which the non-symmetric
+// tangent can respond with a breakdown or a growing residual, and no FP32 correction can
+// reduce the residual further.  The FP64 form has no such floor.
+constexpr double kU32 = 5.9604644775390625e-08;
+constexpr double kCgFloor = 8.0;
+constexpr double kNewtonFloor = 32.0;
+
 static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const double* Pbar, double dt, rve_step_stats& st,
                             const char** why) {
   const int64_t nv = R.nvox;
   const double n9 = 9.0 * (double)nv;
+  double p_floor = 0.0;  // u32 rms(P) at the current iterate (mixed form)
+  auto update_floor = [&]() {
+    if (w.fp32) p_floor = kU32 * rms_of(C, R, false, R.P_work.as<double>(), 9 * nv);
+  };
   LocalStats ls = run_constitutive(C, R, w, R.F_work.as<double>(), nullptr, 0.0, nullptr, dt, true);
   st.local_iters_max = std::max(st.local_iters_max, ls.max_iters);
   if (ls.failures) {
@@ -1033,9 +1143,11 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     *why = "non-finite residual at the initial guess";
     return RVE_ENOCONV;
   }
+  update_floor();
   for (int it = 0; it < C.opt.max_newton; ++it) {
     int done = 0;
-    const int ncg = run_cg(C, R, w, x, keep, done);
+    const double cg_floor = kCgFloor * p_floor;
+    const int ncg = run_cg(C, R, w, x, keep, done, false, cg_floor * cg_floor * n9);
     const CGState cg_end = *R.host_cg;
     st.cg_iters += ncg;
     // A breakdown (negative curvature along p), a diverging or stalled residual or the
@@ -1055,7 +1167,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     }
     st.newton_iters++;
     double lam = 1.0, res_try = 0.0, lam_base = 0.0;
-    bool accepted = false;
+    bool accepted = false, at_floor = false;
     for (int ls_i = 0; ls_i <= C.opt.max_backtrack; ++ls_i) {
       LocalStats l2 = run_constitutive(C, R, w, R.F_work.as<double>(), corr, lam, R.F_try.as<double>(), dt, true,
                                        true, lam_base);
@@ -1065,9 +1177,11 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
         const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
         st.residual_evals++;
         res_try = std::sqrt(rr_t / n9);
+        at_floor = w.fp32 && lam == 1.0 && dF <= C.opt.newton_tol && res_try <= kNewtonFloor * p_floor;
         // a full correction below the tolerance is applied without a decrease test (the
         // residual is then at its rounding floor); otherwise the residual must not grow
-        if (std::isfinite(res_try) && (res_try <= res || (lam == 1.0 && dF <= C.opt.newton_tol && cg_ok))) {
+        if (std::isfinite(res_try) &&
+            (res_try <= res || (lam == 1.0 && dF <= C.opt.newton_tol && cg_ok) || at_floor)) {
           accepted = true;
           break;
         }
@@ -1077,9 +1191,11 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     }
     if (trace_on())
       std::fprintf(stderr,
-                   "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e%s) |dF| %.3e lam %.4g res %.4e -> %.4e%s local_it %d\n",
+                   "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e%s) |dF| %.3e lam %.4g res %.4e -> %.4e%s%s local_it %d "
+                   "floor %.3e\n",
                    it + 1, ncg, done, cg_end.rr / cg_end.rr0, use_best ? ", best iterate" : "", dF, lam, res, res_try,
-                   accepted ? "" : " (line search failed)", st.local_iters_max);
+                   accepted ? "" : " (line search failed)", at_floor ? " (at the FP32 floor)" : "",
+                   st.local_iters_max, p_floor);
     if (!accepted) {
       *why = "residual line search failed";
       return RVE_ENOCONV;
@@ -1090,8 +1206,10 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
     st.dF_norm = dF;
     st.res_norm = res;
     // converged when the full Newton correction (not a line-search fraction of it) of a
-    // usable linear solve is small
-    if (lam == 1.0 && dF <= C.opt.newton_tol && cg_ok) return RVE_OK;
+    // usable linear solve is small, or (mixed form) when such a correction has brought the
+    // residual to its FP32 rounding floor
+    if (lam == 1.0 && dF <= C.opt.newton_tol && (cg_ok || at_floor)) return RVE_OK;
+    update_floor();
   }
   *why = "Newton did not converge within max_newton";
   return RVE_ENOCONV;
@@ -1114,6 +1232,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
     HIPCHECK(hipMemcpyAsync(R.dg.p, R.dg_saved.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, R.stream));
   };
   const char* why = "";
+  int64_t discarded = 0;  // projected applies of failed attempts (not part of the committed solve)
   auto attempt = [&](Work& w, int max_stages) -> int32_t {
     // direct attempt
     Corr9 cr;
@@ -1126,8 +1245,11 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
                      nv, R.stream);
     check_launch("predictor");
     int32_t rc = newton_solve(C, R, w, keep, Pbar, dt, st, &why);
+    st.continuation_stages = 0;
     for (int m = 2; rc != RVE_OK && m <= max_stages; m *= 2) {
       if (trace_on()) std::fprintf(stderr, "[rve] %s; load continuation with %d stages\n", why, m);
+      discarded = (int64_t)st.residual_evals + st.cg_iters;  // the failed solve is not the increment's
+      st.continuation_stages = m;
       restore_dg();
       Corr9 zero;
       for (int c = 0; c < 9; ++c) zero.v[c] = 0.0;
@@ -1157,17 +1279,25 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
     // solve this increment with the FP64 spectral path instead.
     if (trace_on()) std::fprintf(stderr, "[rve] %s in FP32; increment solved again in FP64\n", why);
     restore_dg();
+    discarded = (int64_t)st.residual_evals + st.cg_iters;
     st.fp64_fallback = 1;
     R.fp64_fallbacks++;
     rc = attempt(work(R, false), 16);
   }
   if (rc != RVE_OK) {
     restore_dg();
+    // the tangents now belong to a failed iterate, not to the last converged increment
+    R.w[0].k_ready = R.w[1].k_ready = false;
     HIPCHECK(hipStreamSynchronize(R.stream));
     st.status = rc;
     g_last_error = why;
     return rc;
   }
+  // keep the start-of-increment state (the reverse pass of this increment needs it)
+  HIPCHECK(hipMemcpyAsync(R.Fp_prev.p, R.Fp.p, sizeof(double) * 9 * nv, hipMemcpyDeviceToDevice, R.stream));
+  HIPCHECK(hipMemcpyAsync(R.rho_ssd_prev.p, R.rho_ssd.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, R.stream));
+  HIPCHECK(hipMemcpyAsync(R.rho_gnd_prev.p, R.rho_gnd.p, sizeof(double) * 12 * nv, hipMemcpyDeviceToDevice, R.stream));
+  R.dt_last = dt;
   // commit: Fp and rho_SSD from the converged slip increments, then the Nye tensor
   CommitArgs ca;
   ca.nvox = nv;
@@ -1191,7 +1321,10 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   R.have_prev = true;
   R.increments++;
   st.status = RVE_OK;
-  st.voxel_iterations = (double)nv * (double)(st.residual_evals + st.cg_iters);
+  // the metric counts the projected applies of the solve that produced the committed
+  // increment; those of failed attempts before it are reported separately
+  st.voxel_iterations = (double)nv * (double)((int64_t)st.residual_evals + st.cg_iters - discarded);
+  st.discarded_voxel_iterations = (double)nv * (double)discarded;
   return RVE_OK;
 }
 
@@ -1238,6 +1371,60 @@ static void prepare_device() {
   done.push_back(dev);
 }
 
+// The autotuner: for a grid size and spectral precision, time the z pass (z transforms and
+// the projection of eq. 17) at each candidate tile width (kx columns per block: the widest
+// that the 256-thread block holds, then halvings down to 1) and keep the fastest for the
+// process.  The tile width changes the work split, not the arithmetic of any line or
+// frequency, so the choice does not change results.  Runs once per (grid, precision), on
+// the creating thread, before any worker exists.
+static void autotune_grid(const int32_t n_in[3], bool fp32) {
+  const int n[3] = {n_in[0], n_in[1], n_in[2]};
+  if (tuned_tz(n, fp32) > 0) return;
+  Plan P;
+  build_plan(P, n, fp32, false);
+  const GridPlan base = P.g;
+  std::vector<int> cand;
+  for (int t = base.tz; t >= 1; t /= 2) cand.push_back(t);
+  int best = base.tz;
+  if (cand.size() > 1) {
+    DevBuf spec;
+    spec.alloc(tsize(fp32) * 2 * 9 * (size_t)base.nspec);
+    HIPCHECK(hipMemset(spec.p, 0, spec.bytes));
+    hipStream_t st = nullptr;
+    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    MidArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.op = MID_GREEN;
+    m.spec = spec.p;
+    m.inv_n = 1.0 / (double)base.nvox;
+    float best_ms = 1e30f;
+    for (int t : cand) {
+      GridPlan g = base;
+      g.tz = t;
+      g.ftz = make_fastdiv(t);
+      launch_mid(g, fp32, m, st);  // warm-up
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int r = 0; r < 5; ++r) launch_mid(g, fp32, m, st);
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      check_launch("autotune");
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (trace_on()) std::fprintf(stderr, "[rve] autotune %dx%dx%d %s: tz %d %.2f us\n", n[0], n[1], n[2],
+                                   fp32 ? "fp32" : "fp64", t, 1e3f * ms / 5.f);
+      if (ms < best_ms) best_ms = ms, best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned_tz.push_back({TuneKey{n[0], n[1], n[2], fp32 ? 1 : 0}, best});
+}
+
 extern "C" {
 
 int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt, rve_handle* out) {
@@ -1262,7 +1449,14 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
     HIPCHECK(hipSetDevice(C->device));
     prepare_device();
     C->stream = (hipStream_t)o.stream;
-    if (const char* e = std::getenv("RVE_WORKERS")) C->workers = std::max(1, std::atoi(e));
+    C->workers = o.workers > 0 ? o.workers : settings().workers;
+    C->use_graph = o.use_graph != 0;
+    C->autotune = o.autotune != 0;
+    if (C->autotune)
+      for (int i = 0; i < n_rve; ++i) {
+        autotune_grid(descs[i].n, C->fp32);
+        if (C->fp32) autotune_grid(descs[i].n, false);  // FP64 projection of the correction
+      }
     for (int i = 0; i < n_rve; ++i) {
       C->rves.emplace_back(new RVE());
       init_rve(*C, *C->rves.back(), descs[i]);
@@ -1459,12 +1653,130 @@ int32_t rve_adjoint_solve(rve_handle h, int32_t rve, const uint8_t* mask, const 
   });
 }
 
-// state: per RVE F, F_prev, Fp (9 each), rho_ssd, rho_gnd, dg (12 each), nye, P (9 each),
-// followed by the host scalars.
+int32_t rve_adjoint_increment(rve_handle h, int32_t rve, const uint8_t* mask, const double* dLdP, double* Fp_bar,
+                              double* rho_bar, double* theta_bar, int32_t* cg_iters) {
+  return guarded([&]() -> int32_t {
+    if (!h || rve < 0 || rve >= (int32_t)h->rves.size() || !mask || !dLdP || !Fp_bar || !rho_bar || !theta_bar)
+      throw Error(RVE_EINVAL, "bad argument");
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(dLdP[i])) throw Error(RVE_EINVAL, "non-finite loss weight");
+    HIPCHECK(hipSetDevice(h->device));
+    RVE& R = *h->rves[rve];
+    if (R.increments < 1) throw Error(RVE_ESTATE, "no committed increment to reverse");
+    Work& w = work(R, false);
+    if (!w.plane) throw Error(RVE_EINVAL, "the reverse pass needs the plane kernels (grid planes do not fit in LDS)");
+    const int64_t nv = R.nvox;
+    const size_t f9 = sizeof(double) * 9 * nv, f12 = sizeof(double) * 12 * nv;
+    const int64_t nb = (nv + 63) / 64;
+    if (!R.adj_a9.p) {
+      R.adj_a9.alloc(f9);
+      R.adj_b9.alloc(f9);
+      R.adj_rgb.alloc(f12);
+      R.adj_theta.alloc(sizeof(double) * 4 * nb);
+    }
+    hipStream_t st = R.stream;
+    // 1. the converged state of the increment, re-evaluated from its start-of-increment state
+    //    (the stored slip increments are the warm start): stress, slip increments, tangent
+    HIPCHECK(hipMemcpyAsync(R.dg_saved.p, R.dg.p, f12, hipMemcpyDeviceToDevice, st));
+    ConstArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nvox = nv;
+    a.gid = R.d_gid.as<int32_t>();
+    a.grainR = R.d_R.as<double>();
+    a.mat = R.d_mat.as<MatDev>();
+    a.F = R.F.as<double>();
+    a.Fp_n = R.Fp_prev.as<double>();
+    a.rho_ssd = R.rho_ssd_prev.as<double>();
+    a.rho_gnd = R.rho_gnd_prev.as<double>();
+    a.dg = R.dg_saved.as<double>();
+    a.P = R.P_work.as<double>();
+    a.K = w.K.p;
+    a.k_grouped = 1;
+    a.k_inv_scale = 1.0;
+    a.dt = R.dt_last;
+    a.stats = R.blk.as<int32_t>();
+    a.work = R.blk.as<int32_t>() + 4;
+    launch_constitutive(a, KT_F64, st);
+    check_launch("reverse pass: constitutive");
+    int32_t st4[4];
+    HIPCHECK(hipMemcpyAsync(st4, R.blk.p, sizeof(st4), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (st4[1] != 0) throw Error(RVE_ENOCONV, "local Newton did not converge at the committed state");
+    w.k_ready = true;
+    // 2. right-hand side of the adjoint equilibrium: g = dL/dF at fixed start state
+    AdjointLocalArgs b;
+    std::memset(&b, 0, sizeof(b));
+    for (int i = 0; i < 9; ++i) b.wP[i] = dLdP[i] / (double)nv;
+    b.Fp_bar = Fp_bar;
+    b.rho_bar = rho_bar;
+    b.g = R.adj_a9.as<double>();
+    b.mode = 0;
+    launch_constitutive_adjoint(a, b, st);
+    check_launch("reverse pass: right-hand side");
+    // 3. multiplier: G(K^T : lam) = G(g), lam in the range of G (r = -G(g), x = -lam)
+    double keep[9];
+    for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+    void* x = w.xa.p;
+    run_residual(*h, R, w, R.adj_a9.as<double>(), keep, nullptr, x);
+    int done = 0;
+    const int ncg = run_cg(*h, R, w, x, keep, done, true);
+    if (cg_iters) *cg_iters = ncg;
+    if (!(done == 1 || done == 5)) throw Error(RVE_ENOCONV, "adjoint conjugate gradients did not converge");
+    launch_negate(static_cast<const double*>(x), R.adj_b9.as<double>(), 9 * nv, st);
+    // 4. dL/d(start-of-increment state, parameters) at fixed F with P_bar = dL/dP - lam
+    b.mode = 1;
+    b.lam = R.adj_b9.as<double>();
+    b.g = nullptr;
+    b.Fp_bar_out = Fp_bar;
+    b.rho_bar_out = rho_bar;
+    b.rho_gnd_bar = R.adj_rgb.as<double>();
+    b.theta_partial = R.adj_theta.as<double>();
+    const int nblk = launch_constitutive_adjoint(a, b, st);
+    check_launch("reverse pass: state and parameters");
+    // 5. the start-of-increment GND densities came from the curl of Fp_{k-1} (eqs. 10-13):
+    //    Fp_bar += curl^T (d rho_GND / d alpha)^T rho_gnd_bar at alpha = curl(Fp_{k-1})
+    if (R.mat.hardening && R.mat.c_gnd != 0.0) {
+      const GridPlan& g = w.plan.g;
+      curl_plane64(g, w.spec.p, R.Fp_prev.as<double>(), true, 1.0 / R.h, R.adj_a9.as<double>(), st);
+      launch_gnd_adjoint(nv, R.adj_a9.as<double>(), R.d_gid.as<int32_t>(), R.d_R.as<double>(), R.d_mat.as<MatDev>(),
+                         R.adj_rgb.as<double>(), R.adj_b9.as<double>(), st);
+      curl_plane64(g, w.spec.p, R.adj_b9.as<double>(), false, 1.0 / R.h, R.adj_a9.as<double>(), st);
+      launch_roll_back(g.nx, g.ny, g.nz, R.adj_a9.as<double>(), Fp_bar, st, true);
+      check_launch("reverse pass: GND chain");
+    }
+    // 6. parameter derivatives: block partials summed in a fixed order
+    std::vector<double> part(4 * (size_t)nblk);
+    HIPCHECK(hipMemcpyAsync(part.data(), R.adj_theta.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double th[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < nblk; ++i)
+      for (int j = 0; j < 4; ++j) th[j] += part[4 * (size_t)i + j];
+    theta_bar[1] += th[0];  // K
+    theta_bar[2] += th[1];  // y_c
+    theta_bar[3] += th[2];  // c_gnd
+    theta_bar[0] += th[3];  // tau0 (tau_c held at tau0 without hardening)
+    // 7. first increment: rho_SSD,0 = rho0 = (tau0 / (mu b))^2 / sum_b q^{ab} (uniform), so
+    //    d rho0 / d tau0 = 2 rho0 / tau0 with tau0 = mu b sqrt(sum_b q^{ab} rho0)
+    if (R.increments == 1 && R.mat.hardening) {
+      double rs[12];
+      field_average(*h, R, rho_bar, 12, rs);
+      double sum = 0.0;
+      for (int c = 0; c < 12; ++c) sum += rs[c] * (double)nv;
+      double rowsum = 0.0;
+      for (int c = 0; c < 12; ++c) rowsum += R.mat.q[c];
+      const double tau0 = R.mat.mu * R.mat.burgers * std::sqrt(rowsum * R.rho0);
+      theta_bar[0] += sum * 2.0 * R.rho0 / tau0;
+    }
+    return RVE_OK;
+  });
+}
+
+// state: per RVE F, F_prev, Fp, Nye, P (9 each), rho_ssd, rho_gnd, dg (12 each), the
+// start-of-increment Fp (9), rho_ssd, rho_gnd (12 each), followed by the host scalars.
 int64_t rve_state_bytes(rve_handle h) {
   if (!h) return 0;
   int64_t b = 0;
-  for (auto& r : h->rves) b += (int64_t)sizeof(double) * (9 * 5 + 12 * 3) * r->nvox + (int64_t)sizeof(double) * 40;
+  for (auto& r : h->rves) b += (int64_t)sizeof(double) * (9 * 6 + 12 * 5) * r->nvox + (int64_t)sizeof(double) * 40;
   return b;
 }
 
@@ -1475,9 +1787,10 @@ int32_t rve_save_state(rve_handle h, void* buf) {
     char* o = (char*)buf;
     for (auto& rp : h->rves) {
       RVE& R = *rp;
-      const DevBuf* bufs[8] = {&R.F, &R.F_prev, &R.Fp, &R.nye, &R.P, &R.rho_ssd, &R.rho_gnd, &R.dg};
-      const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
-      for (int i = 0; i < 8; ++i) {
+      const DevBuf* bufs[11] = {&R.F,       &R.F_prev, &R.Fp,      &R.nye,          &R.P,           &R.rho_ssd,
+                                &R.rho_gnd, &R.dg,     &R.Fp_prev, &R.rho_ssd_prev, &R.rho_gnd_prev};
+      const int nc[11] = {9, 9, 9, 9, 9, 12, 12, 12, 9, 12, 12};
+      for (int i = 0; i < 11; ++i) {
         const size_t n = sizeof(double) * nc[i] * R.nvox;
         HIPCHECK(hipMemcpyAsync(o, bufs[i]->p, n, hipMemcpyDeviceToHost, R.stream));
         o += n;
@@ -1489,6 +1802,7 @@ int32_t rve_save_state(rve_handle h, void* buf) {
       std::memcpy(sc + 27, R.Fbar_prev, 72);
       sc[36] = R.have_prev ? 1.0 : 0.0;
       sc[37] = (double)R.increments;
+      sc[38] = R.dt_last;
       std::memcpy(o, sc, sizeof(sc));
       o += sizeof(sc);
       HIPCHECK(hipStreamSynchronize(R.stream));
@@ -1504,9 +1818,10 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
     const char* o = (const char*)buf;
     for (auto& rp : h->rves) {
       RVE& R = *rp;
-      DevBuf* bufs[8] = {&R.F, &R.F_prev, &R.Fp, &R.nye, &R.P, &R.rho_ssd, &R.rho_gnd, &R.dg};
-      const int nc[8] = {9, 9, 9, 9, 9, 12, 12, 12};
-      for (int i = 0; i < 8; ++i) {
+      DevBuf* bufs[11] = {&R.F,       &R.F_prev, &R.Fp,      &R.nye,          &R.P,           &R.rho_ssd,
+                          &R.rho_gnd, &R.dg,     &R.Fp_prev, &R.rho_ssd_prev, &R.rho_gnd_prev};
+      const int nc[11] = {9, 9, 9, 9, 9, 12, 12, 12, 9, 12, 12};
+      for (int i = 0; i < 11; ++i) {
         const size_t n = sizeof(double) * nc[i] * R.nvox;
         HIPCHECK(hipMemcpyAsync(bufs[i]->p, o, n, hipMemcpyHostToDevice, R.stream));
         o += n;
@@ -1520,6 +1835,9 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
       std::memcpy(R.Fbar_prev, sc + 27, 72);
       R.have_prev = sc[36] != 0.0;
       R.increments = (int64_t)sc[37];
+      R.dt_last = sc[38];
+      // the tangents belong to whatever state was evaluated last, not to the loaded one
+      R.w[0].k_ready = R.w[1].k_ready = false;
       HIPCHECK(hipStreamSynchronize(R.stream));
     }
     return RVE_OK;

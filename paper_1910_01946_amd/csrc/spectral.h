@@ -42,6 +42,8 @@ struct CGState {
   double alpha, beta;
   double tol2;     // stop when rr <= tol2 * rr0
   double rr_best;  // smallest r.r so far that was at most a quarter of the previous best
+  double rr_floor; // also stop once rr <= rr_floor: the rounding floor of the right-hand side
+                   // (FP32 spectra), below which no correction is resolved
   int32_t iter;    // completed operator applications
   int32_t done;    // 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 diverging (r.r > 1e4 r0.r0),
                    // 4 max_iter, 5 stalled (|r| not halved within kCgStall iterations)
@@ -114,7 +116,7 @@ __device__ inline void cg_beta_update(CGState* cg, double rr, bool first) {
     cg->rr_best = rr;
     cg->it_best = cg->iter;
   }
-  if (rr <= cg->tol2 * cg->rr0) cg->done = 1;
+  if (rr <= cg->tol2 * cg->rr0 || rr <= cg->rr_floor) cg->done = 1;
   else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;
   else if (cg->iter >= cg->max_iter) cg->done = 4;
   else if (cg->iter - cg->it_best >= kCgStall) cg->done = 5;

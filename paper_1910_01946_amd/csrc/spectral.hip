@@ -432,6 +432,7 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
     cg->tol2 = tol2;
     cg->iter = 0;
     cg->rr_best = rr;
+    cg->rr_floor = 0.0;
     cg->it_best = 0;
     cg->max_iter = max_iter;
     cg->alpha = 0.0;

@@ -38,12 +38,17 @@ inline LaunchEvents& pending_launch_events() {
 
 // Kernel launch for the timed families: when events are pending on the calling thread, the
 // dispatch itself records them at the kernel's start and end (AMD's extended launch), so
-// that their difference is the kernel's own duration.  Errors are left for hipGetLastError.
+// that their difference is the kernel's own duration; otherwise an ordinary launch (which a
+// stream capture records as a graph node).  Errors are left for hipGetLastError.
 template <typename F, typename... Args>
 inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shared_bytes, hipStream_t st, Args... args) {
   LaunchEvents& ev = pending_launch_events();
-  hipExtLaunchKernelGGL(kernel, grid, block, shared_bytes, st, ev.start, ev.stop, 0u, args...);
-  ev = LaunchEvents{};
+  if (ev.start || ev.stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shared_bytes, st, ev.start, ev.stop, 0u, args...);
+    ev = LaunchEvents{};
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shared_bytes, st, args...);
+  }
 }
 
 // Brackets one launch: begin() in the constructor, end() in the destructor.

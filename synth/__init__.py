@@ -310,3 +310,47 @@ def random_field(seed: int, shape, lo: float = -1.0, hi: float = 1.0) -> np.ndar
         z = z ^ (z >> np.uint64(31))
     u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
     return (lo + (hi - lo) * u).reshape(shape)
+
+
+def gaussian_noise(seed: int, n: int) -> np.ndarray:
+    """n standard normal draws: Box-Muller (1958) on pairs of SplitMix64 uniforms, the first
+    uniform shifted to (0, 1] so that its logarithm is finite."""
+    rng = SplitMix64(seed)
+    out = np.empty(n)
+    for i in range(0, n, 2):
+        u1 = 1.0 - rng.uniform()
+        u2 = rng.uniform()
+        r = math.sqrt(-2.0 * math.log(u1))
+        out[i] = r * math.cos(2.0 * math.pi * u2)
+        if i + 1 < n:
+            out[i + 1] = r * math.sin(2.0 * math.pi * u2)
+    return out
+
+
+# Parameters of the adjoint form: the initial critical stress tau0 (it sets the uniform
+# initial SSD density (tau0 / (mu b))^2 / sum_b q^{ab}), the similitude coefficient K of
+# eq. 9, the annihilation distance y_c of eq. 8 and the GND weight c_gnd of eqs. 7 and 9.
+ADJOINT_PARAMS = ("tau0", "K_sim", "y_c", "c_gnd")
+
+
+def with_params(mat: Material, theta) -> Material:
+    """The material with (tau0, K, y_c, c_gnd) = theta; the initial density then follows tau0."""
+    t = [float(v) for v in theta]
+    return mat.replace(tau0=t[0], rho0=0.0, K_sim=t[1], y_c=t[2], c_gnd=t[3])
+
+
+def adjoint_workload(n_override=None, n_inc_override=None):
+    """The 64^3 adjoint workload: 100 Voronoi grains (seed 105), Cu, c_gnd = 1, d = 30 um,
+    tension to 4 % in 40 increments at 1e-4/s.  The initial state is given by tau0 = 3.47 MPa
+    (the critical stress of the annealed density of about 1e11 per system), so that tau0 is one
+    of the differentiated parameters.  Returns (rve, path, theta) with theta = (tau0, K, y_c,
+    c_gnd)."""
+    rves, path = workload("cu64g100", n_override=n_override)
+    rve = rves[0]
+    mat = rve.material
+    theta = (3.47e6, mat.K_sim, mat.y_c, 1.0)
+    rve = dataclasses.replace(rve, material=with_params(mat, theta))
+    if n_inc_override:
+        path = LoadPath(F_bar=path.F_bar[: n_inc_override + 1], P_bar=path.P_bar[: n_inc_override + 1],
+                        mask=path.mask, dt=path.dt)
+    return rve, path, theta

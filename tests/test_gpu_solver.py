@@ -43,23 +43,28 @@ def test_cu16_at_8cubed_fp64_matches_oracle(lib, plane, monkeypatch):
     o, h, out = _run_both(lib, rves[0], path, 3)
     for Po, Pg, Fo, Fg in out:
         scale = np.abs(Po).max()
-        # the solves end at the FP64 rounding floor of the residual (~1e-9 of the stress for
-        # this stiff, low-tau_c case): two GPU builds that differ only in rounding order
-        # already give <P> 1e-10 apart
-        assert np.max(np.abs(Pg - Po)) <= 1e-9 * scale, (Pg, Po)
+        # the FP64 bar of the parity contract (1e-10 relative on <P>); both solvers stop at
+        # |dF| <= 1e-11 and agree to about 2e-13 (the oracle alone moves by 1e-13 when its
+        # tolerances or its FFT axis order change)
+        print("  <P> difference", np.max(np.abs(Pg - Po)) / scale, flush=True)
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * scale, (Pg, Po)
         assert np.max(np.abs(Fg - Fo)) <= 1e-12
     V = rves[0].n_vox
-    assert rel_norm(from_abi(h.field("F")), o.F) < 1e-11
-    assert rel_norm(from_abi(h.field("P")), o.P) < 1e-9      # same rounding floor as <P>
-    assert rel_norm(from_abi(h.field("Fp")), o.Fp) < 1e-11
-    assert rel_norm(from_abi(h.field("rho_ssd"), tensor=False), o.rho_ssd) < 1e-9
+    fields = {"F": rel_norm(from_abi(h.field("F")), o.F), "P": rel_norm(from_abi(h.field("P")), o.P),
+              "Fp": rel_norm(from_abi(h.field("Fp")), o.Fp),
+              "rho_ssd": rel_norm(from_abi(h.field("rho_ssd"), tensor=False), o.rho_ssd)}
+    print("  field differences", fields, flush=True)
+    assert fields["F"] < 1e-11
+    assert fields["P"] < 1e-10
+    assert fields["Fp"] < 1e-11
+    assert fields["rho_ssd"] < 1e-10
 
 
 def _check_gnd_fields(h, o, rve):
-    """Nye tensor and GND densities: the kernels at 1e-12 on the GPU's own committed Fp;
-    the whole increment against 10 x the measured Fp difference relative to |Fp - I| (the
-    curl differentiates Fp - I, and the difference of two converged solutions is rougher
-    than the field)."""
+    """Nye tensor and GND densities: the kernels at 1e-12 on the GPU's own committed Fp; the
+    whole increment at 1e-10 normwise, and below 10 x the measured Fp difference relative to
+    |Fp - I| (the curl differentiates Fp - I, and the difference of two converged solutions
+    is rougher than the field)."""
     Fp = from_abi(h.field("Fp"))
     d_fp = rel_norm(Fp, o.Fp)
     assert d_fp < 1e-11
@@ -69,9 +74,15 @@ def _check_gnd_fields(h, o, rve):
     assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), rho.reshape(-1, 12)) < 1e-12
     fp_dev = np.linalg.norm(o.Fp - np.eye(3)) / np.linalg.norm(o.Fp)
     bound = max(10.0 * d_fp / fp_dev, 1e-12)
-    print("Fp difference", d_fp, "Fp - I relative size", fp_dev, "field bound", bound, flush=True)
-    assert rel_norm(from_abi(h.field("nye")), o.alpha) < bound
-    assert rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd) < bound
+    e_nye = rel_norm(from_abi(h.field("nye")), o.alpha)
+    e_gnd = rel_norm(from_abi(h.field("rho_gnd"), tensor=False), o.rho_gnd)
+    print("Fp difference", d_fp, "Fp - I relative size", fp_dev, "field bound", bound,
+          "Nye", e_nye, "rho_GND", e_gnd, flush=True)
+    # the parity contract's FP64 bar on the Nye and GND fields (1e-10 normwise); the curl
+    # differentiates Fp - I, so the bar is also checked against the Fp difference scaled by
+    # |Fp| / |Fp - I| (measured 1e-11 to 3e-11 against 7e-11 to 2e-10)
+    assert e_nye < min(bound, 1e-10)
+    assert e_gnd < min(bound, 1e-10)
 
 
 def test_cu64_sgcp_at_8cubed_fp64_matches_oracle(lib):
@@ -126,8 +137,8 @@ def test_ragged_grid_fp64_matches_oracle(lib):
     path = synth.uniaxial_tension(0.05, 50, 1e-4)
     o, h, out = _run_both(lib, rve, path, 2, newton_tol=1e-13, cg_tol=1e-12)
     for Po, Pg, Fo, Fg in out:
-        # converged to the FP64 rounding floor of the residual, as in the 8^3 Cu case
-        assert np.max(np.abs(Pg - Po)) <= 1e-9 * np.abs(Po).max()
+        print("  <P> difference", np.max(np.abs(Pg - Po)) / np.abs(Po).max(), flush=True)
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
     _check_gnd_fields(h, o, rve)
 
 
@@ -313,3 +324,54 @@ def test_kernel_timing_counts_live_launches(lib):
     h.timing_start([])
     with pytest.raises(lib.RVEError):
         lib.check(lib.lib().rve_timing_start(h.h, 1 << 9))        # unknown family bit
+
+
+def test_cu64_mixed_runs_the_whole_path_in_fp32_within_1e4_of_the_fp64_form(lib):
+    """The 64^3 strain-gradient workload through all 50 increments (5 % strain) in the mixed
+    form at the benchmark tolerances: no increment falls back to the FP64 spectral path, and
+    <P>_11 stays within 1e-4 (relative to the largest stress of the curve) of the FP64 form at
+    the same tolerances at every increment."""
+    rves, path = synth.workload("cu64")
+    curves = {}
+    for prec in (lib.RVE_MIXED, lib.RVE_FP64):
+        h = lib.Homogenizer(rves, precision=prec, newton_tol=1e-6, cg_tol=1e-3, max_cg=3000, max_newton=150)
+        c = []
+        for k in range(1, path.n_inc + 1):
+            st = h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)[0]
+            if prec == lib.RVE_MIXED:
+                assert st["fp64_fallback"] == 0, (k, st)
+                assert st["discarded_voxel_iterations"] == 0, (k, st)
+            c.append(h.macro()[0][0])
+        h.close()
+        curves[prec] = np.array(c)
+        print(f"precision {prec}: <P>_11 at 5 % {c[-1]:.6e}", flush=True)
+    ref = curves[lib.RVE_FP64]
+    diff = np.abs(curves[lib.RVE_MIXED] - ref) / np.abs(ref).max()
+    print("largest relative <P>_11 difference, mixed vs FP64", diff.max(), flush=True)
+    assert diff.max() <= 1e-4
+
+
+def test_adjoint_solve_refuses_a_tangent_that_is_not_the_committed_increments(lib):
+    """After rve_load_state, and after an increment that failed, the stored tangent belongs to
+    another state than the last committed increment: rve_adjoint_solve refuses until an
+    increment has been taken again."""
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    V = rves[0].n_vox
+    g = cuda(np.zeros((9, V)))
+    h = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    h.step(path.F_bar[1], path.mask, path.P_bar[1], path.dt)
+    state = h.save_state()
+    h.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)
+    h.adjoint_solve(g, path.mask, g.clone())                # valid: the tangent of increment 2
+    h.load_state(state)
+    with pytest.raises(lib.RVEError):
+        h.adjoint_solve(g, path.mask, g.clone())
+    h.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)
+    h.adjoint_solve(g, path.mask, g.clone())
+    h2 = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-15, cg_tol=1e-8, max_newton=1,
+                         max_backtrack=0)
+    h2.load_state(state)
+    with pytest.raises(lib.RVEError):
+        h2.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)   # fails (RVE_ENOCONV)
+    with pytest.raises(lib.RVEError):
+        h2.adjoint_solve(g, path.mask, g.clone())

@@ -154,3 +154,63 @@ def test_fd_fp_sensitivity_step_consistency_and_tangent_identity():
     Fe0 = F @ Gn
     pred = -np.einsum("vijkl,vkl->vij", K, Fe0 @ D) - out["P"] @ np.swapaxes(D, 1, 2) @ np.swapaxes(Gn, 1, 2)
     assert np.abs(pred - S1).max() <= 1e-5 * np.abs(S1).max()
+
+
+def _uniform_point(model, rho_ssd, rho_gnd=0.0):
+    """One voxel whose twelve systems carry the same densities."""
+    return cst.PointData(model, np.zeros(1, dtype=np.int64), np.eye(3)[None],
+                         np.full((1, 12), float(rho_ssd)), np.full((1, 12), float(rho_gnd)))
+
+
+def test_density_update_saturates_at_the_closed_form_fixed_point():
+    """Eqs. 8-9 with all twelve systems slipping equally and no GND term: the mean free path
+    is K / sqrt(11 rho) (the forest of eq. 9 excludes the system itself), so the SSD density
+    stops growing where sqrt(11 rho) / K = 2 y_c rho, i.e. at rho_sat = 11 / (4 y_c^2 K^2)
+    (3.40e14 1/m^2 for Cu).  Along the way u = sqrt(rho) obeys du/dgamma = (sqrt(11)/K -
+    2 y_c u) / (2 b), so rho(gamma) = (u_sat - (u_sat - u_0) exp(-y_c gamma / b))^2.  A forest
+    that included the system itself (12), a dropped factor 2 or 1/b, or K on the wrong side
+    each moves the fixed point or the rate."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=0.0)
+    model = cst.MaterialModel(mat, [[1.0, 0.0, 0.0, 0.0]])
+    b, yc, K = mat.burgers, mat.y_c, mat.K_sim
+    rho_sat = 11.0 / (4.0 * yc ** 2 * K ** 2)
+    assert abs(rho_sat / 3.395e14 - 1) < 1e-3
+    # at the fixed point the density does not move, whatever the slip
+    pd = _uniform_point(model, rho_sat)
+    assert np.abs(pd.h_ssd).max() * rho_sat ** -0.5 < 1e-12 * np.sqrt(11.0) / K
+    out = cst._rho_ssd(pd, np.full((1, 12), 0.3))
+    assert np.allclose(out, rho_sat, rtol=1e-12)
+    # eq. 7 at a uniform forest: tau_c = mu b sqrt(1.975 rho) (Table 1's row sum)
+    mu = elasticity.slip_plane_shear_modulus(mat.C11, mat.C12, mat.C44)
+    assert np.allclose(cst._tau_c(pd), mu * b * np.sqrt(1.975 * rho_sat), rtol=1e-13)
+    # explicit steps of equal slip follow the closed-form saturation curve
+    dgam = 1e-5
+    rho = 1e11
+    u_sat, u0 = np.sqrt(rho_sat), np.sqrt(1e11)
+    checkpoints = (2000, 8000, 40000)
+    for n in range(1, checkpoints[-1] + 1):
+        rho = float(cst._rho_ssd(_uniform_point(model, rho), np.full((1, 12), dgam))[0, 0])
+        if n in checkpoints:
+            exact = (u_sat - (u_sat - u0) * np.exp(-yc * n * dgam / b)) ** 2
+            # first-order steps: error of order y_c dgamma / b relative
+            assert abs(rho / exact - 1) < 2e-3, (n, rho, exact)
+    assert abs(rho / rho_sat - 1) < 1e-4
+
+
+def test_density_fixed_point_doubles_with_an_equal_gnd_forest():
+    """With c_GND = 1 and a GND density equal to the SSD density on every system, the forest
+    of eq. 9 is 2 x 11 rho and the fixed point of eq. 8 doubles: rho_sat = 22 / (4 y_c^2 K^2);
+    eq. 7 then gives tau_c = mu b sqrt(1.975 x 2 rho).  With c_GND = 0 the GND density does not
+    enter at all."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    model = cst.MaterialModel(mat, [[1.0, 0.0, 0.0, 0.0]])
+    rho_sat2 = 22.0 / (4.0 * mat.y_c ** 2 * mat.K_sim ** 2)
+    pd = _uniform_point(model, rho_sat2, rho_sat2)
+    assert np.allclose(cst._rho_ssd(pd, np.full((1, 12), 0.1)), rho_sat2, rtol=1e-12)
+    mu = elasticity.slip_plane_shear_modulus(mat.C11, mat.C12, mat.C44)
+    assert np.allclose(cst._tau_c(pd), mu * mat.burgers * np.sqrt(1.975 * 2 * rho_sat2), rtol=1e-13)
+    mat0 = mat.replace(c_gnd=0.0)
+    model0 = cst.MaterialModel(mat0, [[1.0, 0.0, 0.0, 0.0]])
+    rho_sat = 11.0 / (4.0 * mat.y_c ** 2 * mat.K_sim ** 2)
+    pd0 = _uniform_point(model0, rho_sat, 5 * rho_sat)
+    assert np.allclose(cst._rho_ssd(pd0, np.full((1, 12), 0.1)), rho_sat, rtol=1e-12)

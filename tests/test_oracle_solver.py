@@ -180,3 +180,27 @@ def test_without_gradient_term_voxel_size_does_not_matter():
         rve.voxel_size = h
         out.append(solver.RVESolver(rve).run(path, n_inc=2)[-1]["P_avg"])
     assert np.allclose(out[0], out[1], rtol=0, atol=1e-11 * np.abs(out[0]).max())
+
+
+def test_gradient_term_first_increment_is_size_independent_and_smaller_grains_are_harder():
+    """With the GND term (c_GND = 1) the voxel size h enters only through the Nye tensor of
+    the committed Fp (eq. 12 differentiates with 1/h), and the GND densities are lagged one
+    increment: increment 1 starts from rho_GND = 0 and is identical for every h.  From
+    increment 2 on, a smaller h (smaller grains at the same voxel count) gives larger GND
+    densities, a larger forest in eqs. 7 and 9 and a strictly higher <P>_11: the grain-size
+    effect the paper studies (Section 3).  A GND term entering with the wrong sign, or h
+    entering anywhere else, breaks one of the two."""
+    import dataclasses
+    rves, path = synth.workload("cu64", n_override=4)
+    rve = rves[0]
+    curves = []
+    for fac in (0.25, 1.0, 4.0):
+        r2 = dataclasses.replace(rve, voxel_size=rve.voxel_size * fac)
+        recs = solver.RVESolver(r2, newton_tol=1e-10, cg_tol=1e-8).run(path, n_inc=3)
+        curves.append([rec["P_avg"][0] for rec in recs])
+    first = [c[0] for c in curves]
+    assert max(first) - min(first) <= 1e-13 * abs(first[0]), first
+    for k in (1, 2):
+        seq = [c[k] for c in curves]
+        assert seq[0] > seq[1] > seq[2], (k, seq)
+        assert seq[0] / seq[2] - 1 > 1e-2, (k, seq)
