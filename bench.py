@@ -211,6 +211,35 @@ def timed(h, path, first, K, tag):
     return {"T": time.perf_counter() - t0, "vi": vi, "discarded_vi": disc, "per_increment": per_inc, "P11": P}
 
 
+class ProfilerRegion:
+    """The replay is the region a profiler run with rocprofv3 --selected-regions records:
+    roctxProfilerResume(0) before it and roctxProfilerPause(0) after it (no effect without a
+    profiler; skipped if the ROCm tracer library is absent)."""
+
+    def __init__(self):
+        import ctypes
+        self.L = None
+        for name in ("libroctx64.so", "/opt/rocm/lib/libroctx64.so"):
+            try:
+                self.L = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        if self.L is not None:
+            self.L.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+            self.L.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+
+    def __enter__(self):
+        if self.L is not None:
+            self.L.roctxProfilerResume(0)
+        return self
+
+    def __exit__(self, *exc):
+        if self.L is not None:
+            self.L.roctxProfilerPause(0)
+        return False
+
+
 def roofline_replay(lib, rves, path, state, first, R, opts):
     """Serialised replay (one host worker, so RVEs and kernels do not overlap) of R increments
     from the saved state, with kernel-timing events on every family."""
@@ -218,9 +247,10 @@ def roofline_replay(lib, rves, path, state, first, R, opts):
     h.load_state(state)
     h.timing_start(list(FAMILY_KERNELS))
     t0 = time.perf_counter()
-    for k in range(first, first + R):
-        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
-        print(f"[serialised replay with events] increment {k} done", file=sys.stderr, flush=True)
+    with ProfilerRegion():
+        for k in range(first, first + R):
+            h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+            print(f"[serialised replay with events] increment {k} done", file=sys.stderr, flush=True)
     T = time.perf_counter() - t0
     fam = {f: h.timing_read(f) for f in FAMILY_KERNELS}
     h.timing_start(())

@@ -71,6 +71,10 @@ typedef struct {
   const double* grain_quat;      /* host, n_grains x (w, x, y, z), crystal -> sample; copied and
                                     normalised                                                  */
   rve_material material;         /* by value                                                     */
+  const double* grain_elastic;   /* host, n_grains x (C11, C12, C44) in Pa, cubic in the crystal
+                                    frame (eq. 4), copied; NULL: the material's constants for
+                                    every grain.  Lets one RVE hold phases of different stiffness
+                                    (for instance the elastic three-phase cell of Appendix B)    */
 } rve_desc;
 
 typedef struct {
@@ -94,6 +98,19 @@ typedef struct {
   int32_t autotune;      /* 1: time the candidate z-pass tile widths of each grid size once
                             per process at rve_create and keep the fastest (the tile width
                             does not change any result); 0: the fixed rule                   */
+  int32_t max_cutbacks;  /* automatic time-step cut-back: an increment that fails with
+                            RVE_ENOCONV is replaced by two increments of dt/2 (targets
+                            interpolated linearly in time), each committed, halved again up to
+                            this many levels; 0 (default): no cut-back.  Changes the time
+                            integration where it acts (the result equals explicit half steps) */
+  int32_t max_continuation; /* load-continuation stages (1, 2, 4, ... up to this value) that the
+                            FP64 path may take to solve a failed increment with the same dt and
+                            the same result; 0: 16; 1: none                                   */
+  int32_t frequencies;   /* 0: the rotated-scheme frequencies of Appendix A (eq. A.4), the
+                            paper's method; 1: standard frequencies (the continuous derivative
+                            of the trigonometric interpolant, k = xi, Nyquist derivative 0), the
+                            comparison of Appendix B.  Both the projection of eq. 17 and the
+                            curl of eq. 12 use the chosen scheme; the reverse pass needs 0    */
 } rve_options;
 
 /* Per-RVE statistics of one increment. */
@@ -115,6 +132,9 @@ typedef struct {
   double discarded_voxel_iterations; /* nvox * projected applies of failed attempts before the
                                 committed solve (counted in newton_iters, cg_iters and
                                 residual_evals, not in voxel_iterations)                       */
+  int32_t cutbacks;          /* time-step halvings taken (max_cutbacks > 0): the increment was
+                                committed as cutbacks + 1 sub-increments                        */
+  int32_t pad;
 } rve_step_stats;
 
 /* Create a handle holding n_rve RVEs (Section 2.2).  Per grain: rotation from the

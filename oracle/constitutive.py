@@ -50,12 +50,18 @@ from . import elasticity, tables
 class MaterialModel:
     """Per-grain tables of one RVE: sample-frame stiffness and Schmid tensors."""
 
-    def __init__(self, mat, quats):
+    def __init__(self, mat, quats, grain_elastic=None):
         self.mat = mat
         R = elasticity.quat_to_matrix(np.asarray(quats, dtype=np.float64))   # (G, 3, 3)
         self.R = R
-        C0 = elasticity.cubic_stiffness(mat.C11, mat.C12, mat.C44)
-        self.C = elasticity.rotate4(C0, R)                                    # (G, 3,3,3,3)
+        if grain_elastic is None:
+            C0 = elasticity.cubic_stiffness(mat.C11, mat.C12, mat.C44)
+            self.C = elasticity.rotate4(C0, R)                                # (G, 3,3,3,3)
+        else:
+            # a cubic stiffness per grain (phases of different stiffness)
+            ge = np.asarray(grain_elastic, dtype=np.float64).reshape(-1, 3)
+            self.C = np.stack([elasticity.rotate4(elasticity.cubic_stiffness(*ge[g]), R[g:g + 1])[0]
+                               for g in range(R.shape[0])])
         s0, m0 = tables.slip_systems()
         s = np.einsum("gij,aj->gai", R, s0)
         m = np.einsum("gij,aj->gai", R, m0)

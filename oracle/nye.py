@@ -23,9 +23,9 @@ import numpy as np
 from . import elasticity, spectral, tables
 
 
-def nye_tensor(Fp: np.ndarray, h: float) -> np.ndarray:
+def nye_tensor(Fp: np.ndarray, h: float, scheme="rotated") -> np.ndarray:
     """alpha (nz, ny, nx, 3, 3) of the plastic deformation gradient field (eq. 12)."""
-    return spectral.curl(Fp, h)
+    return spectral.curl(Fp, h, scheme)
 
 
 def segment_densities(alpha: np.ndarray, gid: np.ndarray, quats, burgers: float) -> np.ndarray:
@@ -44,8 +44,8 @@ def system_densities(rho_seg: np.ndarray) -> np.ndarray:
     return edge + 0.5 * screw[..., screw_of]
 
 
-def gnd_from_fp(Fp, h, gid, quats, burgers):
-    alpha = nye_tensor(Fp, h)
+def gnd_from_fp(Fp, h, gid, quats, burgers, scheme="rotated"):
+    alpha = nye_tensor(Fp, h, scheme)
     seg = segment_densities(alpha, gid, quats, burgers)
     return alpha, seg, system_densities(seg)
 

@@ -79,10 +79,11 @@ class RVESolver:
     """State and increment loop of one RVE (synth.RVE)."""
 
     def __init__(self, rve, newton_tol=1e-11, cg_tol=1e-10, max_newton=40, max_cg=5000,
-                 max_backtrack=12):
+                 max_backtrack=12, scheme="rotated"):
         self.rve = rve
         self.mat = rve.material
-        self.model = constitutive.MaterialModel(rve.material, rve.quats)
+        self.model = constitutive.MaterialModel(rve.material, rve.quats, getattr(rve, "grain_elastic", None))
+        self.scheme = scheme
         self.shape = rve.grain_of_voxel.shape          # (nz, ny, nx)
         self.V = int(np.prod(self.shape))
         self.gid = rve.grain_of_voxel.reshape(-1)
@@ -111,7 +112,7 @@ class RVESolver:
         return a.reshape((self.V,) + a.shape[3:])
 
     def project(self, A, mask, dc_target=None):
-        return self.flat(spectral.project(self.field(A), mask, dc_target))
+        return self.flat(spectral.project(self.field(A), mask, dc_target, self.scheme))
 
     # ---- one increment -------------------------------------------------------------
     def step(self, F_bar, mask, P_bar, dt):
@@ -181,7 +182,7 @@ class RVESolver:
         self.rho_ssd = out["rho_ssd"]
         self.F_bar_prev = F_bar
         alpha, _, rho_gnd = nye.gnd_from_fp(self.field(self.Fp), self.h, self.rve.grain_of_voxel,
-                                            self.rve.quats, self.mat.burgers)
+                                            self.rve.quats, self.mat.burgers, scheme=self.scheme)
         self.alpha = self.flat(alpha)
         self.rho_gnd = self.flat(rho_gnd)
         return stats

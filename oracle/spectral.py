@@ -57,9 +57,30 @@ def modified_frequencies(shape_zyx):
     return np.broadcast_arrays(kx, ky, kz)
 
 
-def kvector(shape_zyx) -> np.ndarray:
-    """(nz, ny, nx, 3) complex modified frequency vector."""
-    kx, ky, kz = modified_frequencies(shape_zyx)
+def standard_frequencies(shape_zyx):
+    """xi_x, xi_y, xi_z in radians per voxel on the (nz, ny, nx) frequency grid, each index q
+    read as the signed frequency q or q - n in [-n/2, n/2); the Nyquist frequency (q = n/2 of
+    an even n) gets 0: the trigonometric interpolant's derivative there is not a real field."""
+    def axis(n):
+        q = np.arange(n)
+        xi = 2.0 * np.pi * np.where(q <= (n - 1) // 2, q, q - n) / n
+        if n % 2 == 0:
+            xi[n // 2] = 0.0
+        return xi.astype(np.complex128)
+    nz, ny, nx = shape_zyx
+    return np.broadcast_arrays(axis(nx)[None, None, :], axis(ny)[None, :, None], axis(nz)[:, None, None])
+
+
+def kvector(shape_zyx, scheme="rotated") -> np.ndarray:
+    """(nz, ny, nx, 3) complex frequency vector: the modified frequencies of the rotated scheme
+    (eq. A.4, the paper's method) or, with scheme="standard", the plain frequencies xi (the
+    comparison of Appendix B)."""
+    if scheme == "standard":
+        kx, ky, kz = standard_frequencies(shape_zyx)
+    elif scheme == "rotated":
+        kx, ky, kz = modified_frequencies(shape_zyx)
+    else:
+        raise ValueError(scheme)
     return np.stack([kx, ky, kz], axis=-1)
 
 
@@ -94,9 +115,9 @@ def project_hat(A_hat: np.ndarray, k: np.ndarray, mask_F, dc_target=None) -> np.
     return out
 
 
-def project(A: np.ndarray, mask_F, dc_target=None) -> np.ndarray:
+def project(A: np.ndarray, mask_F, dc_target=None, scheme="rotated") -> np.ndarray:
     """Real-space projection G(A) of a real tensor field (nz, ny, nx, 3, 3), eq. 17."""
-    k = kvector(A.shape[:3])
+    k = kvector(A.shape[:3], scheme)
     return ifft3_real(project_hat(fft3(A), k, mask_F, dc_target))
 
 
@@ -105,17 +126,24 @@ LEVI_CIVITA[0, 1, 2] = LEVI_CIVITA[1, 2, 0] = LEVI_CIVITA[2, 0, 1] = 1.0
 LEVI_CIVITA[0, 2, 1] = LEVI_CIVITA[2, 1, 0] = LEVI_CIVITA[1, 0, 2] = -1.0
 
 
-def curl(Fp: np.ndarray, h: float) -> np.ndarray:
+def curl(Fp: np.ndarray, h: float, scheme="rotated") -> np.ndarray:
     """alpha_ij = eps_jml d_m Fp_il with the rotated-scheme derivative (eq. 12, eq. B.3)."""
-    k = kvector(Fp.shape[:3])
+    k = kvector(Fp.shape[:3], scheme)
     Fh = fft3(Fp - np.eye(3))
     ah = np.einsum("jml,zyxm,zyxil->zyxij", LEVI_CIVITA, 1j * k / h, Fh)
     return ifft3_real(ah)
 
 
-def gradient(u: np.ndarray, h: float) -> np.ndarray:
+def gradient(u: np.ndarray, h: float, scheme="rotated") -> np.ndarray:
     """Rotated-scheme discrete gradient of a periodic vector field u (nz, ny, nx, 3):
     F_ij = d_j u_i, i.e. F_hat_ij = (i k_j / h) u_hat_i."""
-    k = kvector(u.shape[:3])
+    k = kvector(u.shape[:3], scheme)
     uh = fft3(u)
     return ifft3_real(np.einsum("zyxi,zyxj->zyxij", uh, 1j * k / h))
+
+
+def derivative(f: np.ndarray, axis: int, h: float, scheme="rotated") -> np.ndarray:
+    """d f / d x_axis of a real periodic scalar field f (nz, ny, nx) with the derivative of the
+    scheme (axis 0 = x): i k_axis / h in Fourier space."""
+    k = kvector(f.shape, scheme)[..., axis]
+    return ifft3_real(fft3(f) * (1j * k / h))

@@ -44,7 +44,8 @@ class Homogenizer:
     """A set of RVEs advanced together through rve_step_increment."""
 
     def __init__(self, rves, precision=RVE_FP64, newton_tol=1e-10, cg_tol=1e-8, max_newton=40,
-                 max_cg=2000, max_backtrack=12, device=0, stream=None, use_graph=0, workers=0, autotune=0):
+                 max_cg=2000, max_backtrack=12, device=0, stream=None, use_graph=0, workers=0, autotune=0,
+                 max_cutbacks=0, max_continuation=0, frequencies=0):
         L = lib()
         n = len(rves)
         self._keep = []
@@ -60,10 +61,16 @@ class Homogenizer:
             d.grain_of_voxel = gid.ctypes.data_as(C.POINTER(C.c_int32))
             d.grain_quat = _dp(q)
             d.material = make_material(r.material)
+            ge = getattr(r, "grain_elastic", None)
+            if ge is not None:
+                ge = np.ascontiguousarray(ge, dtype=np.float64).reshape(-1)
+                self._keep.append(ge)
+                d.grain_elastic = _dp(ge)
         opt = rve_options(precision=precision, newton_tol=newton_tol, cg_tol=cg_tol, max_newton=max_newton,
                           max_cg=max_cg, max_backtrack=max_backtrack, device=device,
                           stream=C.c_void_p(stream) if stream else None, use_graph=int(use_graph),
-                          workers=int(workers), autotune=int(autotune))
+                          workers=int(workers), autotune=int(autotune), max_cutbacks=int(max_cutbacks),
+                          max_continuation=int(max_continuation), frequencies=int(frequencies))
         h = C.c_void_p()
         check(L.rve_create(descs, n, C.byref(opt), C.byref(h)))
         self.h = h

@@ -24,14 +24,15 @@ class rve_material(C.Structure):
 class rve_desc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("voxel_size", C.c_double), ("n_grains", C.c_int32),
                 ("grain_of_voxel", C.POINTER(C.c_int32)), ("grain_quat", C.POINTER(C.c_double)),
-                ("material", rve_material)]
+                ("material", rve_material), ("grain_elastic", C.POINTER(C.c_double))]
 
 
 class rve_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("newton_tol", C.c_double), ("cg_tol", C.c_double),
                 ("max_newton", C.c_int32), ("max_cg", C.c_int32), ("max_backtrack", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("use_graph", C.c_int32),
-                ("workers", C.c_int32), ("autotune", C.c_int32)]
+                ("workers", C.c_int32), ("autotune", C.c_int32), ("max_cutbacks", C.c_int32),
+                ("max_continuation", C.c_int32), ("frequencies", C.c_int32)]
 
 
 class rve_step_stats(C.Structure):
@@ -39,7 +40,8 @@ class rve_step_stats(C.Structure):
                 ("residual_evals", C.c_int32), ("line_search_cuts", C.c_int32),
                 ("local_iters_max", C.c_int32), ("res_norm", C.c_double), ("dF_norm", C.c_double),
                 ("voxel_iterations", C.c_double), ("fp64_fallback", C.c_int32),
-                ("continuation_stages", C.c_int32), ("discarded_voxel_iterations", C.c_double)]
+                ("continuation_stages", C.c_int32), ("discarded_voxel_iterations", C.c_double),
+                ("cutbacks", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -245,9 +245,15 @@ __device__ __forceinline__ void setup_point(const ConstArgs& args, const MatDev&
   }
   to_crystal(Rg, Fs, Fc);
   to_crystal(Rg, Fps, Fpc);
-  p.C11 = M.C11;
-  p.C12 = M.C12;
-  p.C44 = M.C44;
+  if (args.grainC) {
+    p.C11 = args.grainC[3 * g];
+    p.C12 = args.grainC[3 * g + 1];
+    p.C44 = args.grainC[3 * g + 2];
+  } else {
+    p.C11 = M.C11;
+    p.C12 = M.C12;
+    p.C44 = M.C44;
+  }
   p.a = args.dt * M.gamma0_dot;
   inv3(Fpc, p.Gn);
   mm3(Fc, p.Gn, p.Fe0);

@@ -24,6 +24,7 @@ struct ConstArgs {
   int64_t nvox;
   const int32_t* gid;
   const double* grainR;          // 9 per grain, crystal -> sample
+  const double* grainC;          // C11, C12, C44 per grain, or null: the material's (MatDev)
   const MatDev* mat;
   const double* F;               // evaluated at F + lam * dF (dF may be null)
   const double* dF;              // FP64 correction field, may be null

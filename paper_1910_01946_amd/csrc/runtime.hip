@@ -312,6 +312,7 @@ static void plan_geometry(GridPlan& g, const int n[3], int tz_choice = 0) {
   g.fnxh = make_fastdiv(g.nxh);
   g.fnz = make_fastdiv(g.nz);
   g.ftz = make_fastdiv(g.tz);
+  g.freq = FREQ_ROTATED;
 }
 
 // Tile widths chosen by the autotuner, per (grid, spectral precision), for the whole process.
@@ -330,9 +331,10 @@ static int tuned_tz(const int n[3], bool fp32) {
   return 0;
 }
 
-static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false) {
+static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false, int freq = FREQ_ROTATED) {
   GridPlan& g = P.g;
   plan_geometry(g, n, autotune ? tuned_tz(n, fp32) : 0);
+  g.freq = freq;
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
     const int m = n[d];
@@ -524,6 +526,8 @@ struct RVE {
   DevBuf proj_spec, x64;
   bool proj_ready = false;
   bool autotune = false;          // plans take the autotuned z-pass tile width
+  int freq = FREQ_ROTATED;        // frequency scheme of the projection and the curl
+  DevBuf d_C;                     // per-grain C11, C12, C44 (empty: the material's)
   LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
     if (host_cg) (void)hipHostFree(host_cg);
@@ -535,6 +539,7 @@ struct RVE {
   bool have_prev = false;
   double Favg[9], Favg_prev[9], Pavg[9];
   double Fbar_prev[9];
+  double Pbar_prev[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // stress targets of the last increment
   int64_t increments = 0;
 };
 
@@ -543,6 +548,9 @@ struct Ctx {
   bool fp32 = false;
   int workers = 8;               // host threads driving RVEs concurrently
   bool use_graph = false;        // CG chunks as captured HIP graphs
+  int freq = FREQ_ROTATED;       // frequency scheme of the projection and the curl
+  int max_cutbacks = 0;          // halvings of the time step of a failed increment
+  int max_continuation = 16;     // load-continuation stages of a failed FP64 attempt
   bool autotune = false;         // autotuned z-pass tile widths
   rve_options opt;
   hipStream_t stream = nullptr;  // caller's stream (optional)
@@ -559,7 +567,7 @@ static Work& work(RVE& R, bool fp32) {
   Work& w = R.w[fp32 ? 1 : 0];
   if (!w.ready) {
     w.fp32 = fp32;
-    build_plan(w.plan, R.n, fp32, R.autotune);
+    build_plan(w.plan, R.n, fp32, R.autotune, R.freq);
     const int64_t nv = R.nvox;
     const size_t ts = tsize(fp32);
     // grouped layout: G groups of W entries per voxel (see tangent_index)
@@ -601,6 +609,16 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   }
   R.mat = make_material(d.material);
   R.rho0 = initial_rho0(d.material, R.mat);
+  R.freq = C.freq;
+  if (d.grain_elastic) {
+    for (int gi = 0; gi < d.n_grains; ++gi) {
+      const double* c = d.grain_elastic + 3 * gi;
+      if (!(std::isfinite(c[0]) && std::isfinite(c[1]) && std::isfinite(c[2]) && c[2] > 0.0 && c[0] - c[1] > 0.0 &&
+            c[0] + 2.0 * c[1] > 0.0))
+        throw Error(RVE_EINVAL, "elastic constants of grain " + std::to_string(gi) + " are not positive definite");
+    }
+    upload(R.d_C, d.grain_elastic, sizeof(double) * 3 * (size_t)d.n_grains);
+  }
   upload(R.d_mat, &R.mat, sizeof(MatDev));
   upload(R.d_gid, d.grain_of_voxel, sizeof(int32_t) * R.nvox);
   upload(R.d_R, Rg.data(), sizeof(double) * Rg.size());
@@ -665,6 +683,7 @@ static LocalStats run_constitutive(Ctx& C, RVE& R, Work& w, const double* F, con
   a.nvox = R.nvox;
   a.gid = R.d_gid.as<int32_t>();
   a.grainR = R.d_R.as<double>();
+  a.grainC = R.d_C.as<double>();
   a.mat = R.d_mat.as<MatDev>();
   a.F = F;
   a.dF = dF;
@@ -754,7 +773,7 @@ static void project_field(const GridPlan& g, bool fp32, bool plane, void* spec, 
 static const double* newton_correction(RVE& R, Work& w, const void* x, const double* keep) {
   if (!w.fp32) return static_cast<const double*>(x);
   if (!R.proj_ready) {
-    build_plan(R.proj_plan, R.n, false, R.autotune);
+    build_plan(R.proj_plan, R.n, false, R.autotune, R.freq);
     R.proj_spec.alloc(tsize(false) * 2 * 9 * R.proj_plan.g.nspec);
     R.x64.alloc(sizeof(double) * 9 * (size_t)R.nvox);
     R.proj_ready = true;
@@ -1273,7 +1292,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
     return rc;
   };
   // FP32: one direct attempt, then the FP64 path with load continuation
-  int32_t rc = attempt(work(R, C.fp32), C.fp32 ? 1 : 16);
+  int32_t rc = attempt(work(R, C.fp32), C.fp32 ? 1 : C.max_continuation);
   if (rc != RVE_OK && C.fp32) {
     // FP32 conjugate gradients stall near kappa * eps_32 on ill-conditioned tangents;
     // solve this increment with the FP64 spectral path instead.
@@ -1282,7 +1301,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
     discarded = (int64_t)st.residual_evals + st.cg_iters;
     st.fp64_fallback = 1;
     R.fp64_fallbacks++;
-    rc = attempt(work(R, false), 16);
+    rc = attempt(work(R, false), C.max_continuation);
   }
   if (rc != RVE_OK) {
     restore_dg();
@@ -1318,6 +1337,7 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   field_average(C, R, R.F.as<double>(), 9, R.Favg);
   field_average(C, R, R.P.as<double>(), 9, R.Pavg);
   std::memcpy(R.Fbar_prev, Fbar, sizeof(double) * 9);
+  std::memcpy(R.Pbar_prev, Pbar, sizeof(double) * 9);
   R.have_prev = true;
   R.increments++;
   st.status = RVE_OK;
@@ -1326,6 +1346,54 @@ static int32_t step_rve(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask,
   st.voxel_iterations = (double)nv * (double)((int64_t)st.residual_evals + st.cg_iters - discarded);
   st.discarded_voxel_iterations = (double)nv * (double)discarded;
   return RVE_OK;
+}
+
+// Automatic time-step cut-back: an increment that fails (after the solver's own retries) is
+// replaced by two increments of half the time step, to the midpoint of the macroscopic
+// targets (both the prescribed F and the prescribed P interpolate linearly in time) and then
+// to the end point, each committed like any increment; a half that fails is halved again,
+// down to max_cutbacks levels.  Unlike the load continuation inside step_rve (which changes
+// only the iteration path of one increment), a cut-back changes the time integration: the
+// state is committed at the midpoint, so the result equals that of two explicit increments.
+// st accumulates the counts of every attempt; st.cutbacks counts the halvings.
+static int32_t step_with_cutback(Ctx& C, RVE& R, const double* Fbar, const uint8_t* mask, const double* Pbar, double dt,
+                                 int depth, rve_step_stats& st) {
+  rve_step_stats s1;
+  const int32_t rc = step_rve(C, R, Fbar, mask, Pbar, dt, s1);
+  auto add = [&](const rve_step_stats& a) {
+    st.newton_iters += a.newton_iters;
+    st.cg_iters += a.cg_iters;
+    st.residual_evals += a.residual_evals;
+    st.line_search_cuts += a.line_search_cuts;
+    st.local_iters_max = std::max(st.local_iters_max, a.local_iters_max);
+    st.res_norm = a.res_norm;
+    st.dF_norm = a.dF_norm;
+    st.fp64_fallback |= a.fp64_fallback;
+    st.continuation_stages = std::max(st.continuation_stages, a.continuation_stages);
+    if (a.status == RVE_OK) {
+      st.voxel_iterations += a.voxel_iterations;
+      st.discarded_voxel_iterations += a.discarded_voxel_iterations;
+    } else {
+      // every projected apply of a failed attempt is discarded
+      st.discarded_voxel_iterations += (double)R.nvox * (double)(a.residual_evals + a.cg_iters);
+    }
+  };
+  add(s1);
+  if (rc == RVE_OK || rc != RVE_ENOCONV || depth >= C.max_cutbacks) {
+    st.status = rc;
+    return rc;
+  }
+  if (trace_on()) std::fprintf(stderr, "[rve] increment failed; time step cut back to dt / %d\n", 2 << depth);
+  st.cutbacks += 1;
+  double Fm[9], Pm[9];
+  for (int c = 0; c < 9; ++c) {
+    Fm[c] = 0.5 * (R.Fbar_prev[c] + Fbar[c]);
+    Pm[c] = 0.5 * (R.Pbar_prev[c] + Pbar[c]);
+  }
+  int32_t r = step_with_cutback(C, R, Fm, mask, Pm, 0.5 * dt, depth + 1, st);
+  if (r == RVE_OK) r = step_with_cutback(C, R, Fbar, mask, Pbar, 0.5 * dt, depth + 1, st);
+  st.status = r;
+  return r;
 }
 
 }  // namespace rve
@@ -1451,6 +1519,11 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
     C->stream = (hipStream_t)o.stream;
     C->workers = o.workers > 0 ? o.workers : settings().workers;
     C->use_graph = o.use_graph != 0;
+    if (o.max_cutbacks < 0 || o.max_cutbacks > 10 || o.max_continuation < 0) throw Error(RVE_EINVAL, "bad solver options");
+    C->max_cutbacks = o.max_cutbacks;
+    if (o.frequencies != FREQ_ROTATED && o.frequencies != FREQ_STANDARD) throw Error(RVE_EINVAL, "unknown frequency scheme");
+    C->freq = o.frequencies;
+    C->max_continuation = o.max_continuation > 0 ? o.max_continuation : 16;
     C->autotune = o.autotune != 0;
     if (C->autotune)
       for (int i = 0; i < n_rve; ++i) {
@@ -1541,7 +1614,12 @@ int32_t rve_step_increment(rve_handle h, const double* F_bar, const uint8_t* mas
         const int i = next.fetch_add(1);
         if (i >= nr) break;
         try {
-          rcs[i] = step_rve(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, st[i]);
+          if (h->max_cutbacks > 0) {
+            std::memset(&st[i], 0, sizeof(st[i]));
+            rcs[i] = step_with_cutback(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, 0, st[i]);
+          } else {
+            rcs[i] = step_rve(*h, *h->rves[i], F_bar + 9 * i, mask, Pb + 9 * i, dt, st[i]);
+          }
           if (rcs[i] != RVE_OK) msgs[i] = g_last_error;
         } catch (const Error& e) {
           rcs[i] = e.code;
@@ -1665,6 +1743,7 @@ int32_t rve_adjoint_increment(rve_handle h, int32_t rve, const uint8_t* mask, co
     if (R.increments < 1) throw Error(RVE_ESTATE, "no committed increment to reverse");
     Work& w = work(R, false);
     if (!w.plane) throw Error(RVE_EINVAL, "the reverse pass needs the plane kernels (grid planes do not fit in LDS)");
+    if (R.freq != FREQ_ROTATED) throw Error(RVE_EINVAL, "the reverse pass needs the rotated-scheme frequencies");
     const int64_t nv = R.nvox;
     const size_t f9 = sizeof(double) * 9 * nv, f12 = sizeof(double) * 12 * nv;
     const int64_t nb = (nv + 63) / 64;
@@ -1683,6 +1762,7 @@ int32_t rve_adjoint_increment(rve_handle h, int32_t rve, const uint8_t* mask, co
     a.nvox = nv;
     a.gid = R.d_gid.as<int32_t>();
     a.grainR = R.d_R.as<double>();
+    a.grainC = R.d_C.as<double>();
     a.mat = R.d_mat.as<MatDev>();
     a.F = R.F.as<double>();
     a.Fp_n = R.Fp_prev.as<double>();
@@ -1776,7 +1856,7 @@ int32_t rve_adjoint_increment(rve_handle h, int32_t rve, const uint8_t* mask, co
 int64_t rve_state_bytes(rve_handle h) {
   if (!h) return 0;
   int64_t b = 0;
-  for (auto& r : h->rves) b += (int64_t)sizeof(double) * (9 * 6 + 12 * 5) * r->nvox + (int64_t)sizeof(double) * 40;
+  for (auto& r : h->rves) b += (int64_t)sizeof(double) * (9 * 6 + 12 * 5) * r->nvox + (int64_t)sizeof(double) * 48;
   return b;
 }
 
@@ -1795,7 +1875,7 @@ int32_t rve_save_state(rve_handle h, void* buf) {
         HIPCHECK(hipMemcpyAsync(o, bufs[i]->p, n, hipMemcpyDeviceToHost, R.stream));
         o += n;
       }
-      double sc[40] = {0};
+      double sc[48] = {0};
       std::memcpy(sc, R.Favg, 72);
       std::memcpy(sc + 9, R.Favg_prev, 72);
       std::memcpy(sc + 18, R.Pavg, 72);
@@ -1803,6 +1883,7 @@ int32_t rve_save_state(rve_handle h, void* buf) {
       sc[36] = R.have_prev ? 1.0 : 0.0;
       sc[37] = (double)R.increments;
       sc[38] = R.dt_last;
+      std::memcpy(sc + 39, R.Pbar_prev, 72);
       std::memcpy(o, sc, sizeof(sc));
       o += sizeof(sc);
       HIPCHECK(hipStreamSynchronize(R.stream));
@@ -1826,7 +1907,7 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
         HIPCHECK(hipMemcpyAsync(bufs[i]->p, o, n, hipMemcpyHostToDevice, R.stream));
         o += n;
       }
-      double sc[40];
+      double sc[48];
       std::memcpy(sc, o, sizeof(sc));
       o += sizeof(sc);
       std::memcpy(R.Favg, sc, 72);
@@ -1836,6 +1917,7 @@ int32_t rve_load_state(rve_handle h, const void* buf) {
       R.have_prev = sc[36] != 0.0;
       R.increments = (int64_t)sc[37];
       R.dt_last = sc[38];
+      std::memcpy(R.Pbar_prev, sc + 39, 72);
       // the tangents belong to whatever state was evaluated last, not to the loaded one
       R.w[0].k_ready = R.w[1].k_ready = false;
       HIPCHECK(hipStreamSynchronize(R.stream));

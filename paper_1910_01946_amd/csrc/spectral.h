@@ -21,7 +21,16 @@ struct GridPlan {
   int ty;            // kx columns per block in the y passes
   int tz;            // kx columns per block in the z pass
   FastDiv fnx, fnxh, fnz, ftz;  // divisions by nx, nxh, nz, tz
+  int freq;          // FREQ_ROTATED (eq. A.4) or FREQ_STANDARD (continuous frequencies)
 };
+
+// Frequency vector of the derivative i k / h in the projection and the curl.
+//   FREQ_ROTATED:  k_i = 1/4 (-i)(E_i - 1) prod_{j != i} (1 + E_j), E = exp(i xi) (eq. A.4): the
+//                  rotated finite-difference scheme the paper uses;
+//   FREQ_STANDARD: k_i = xi_i in (-pi, pi), the continuous derivative of the trigonometric
+//                  interpolant, with the Nyquist frequency's derivative set to 0 (the
+//                  comparison of Appendix B).
+enum FreqScheme { FREQ_ROTATED = 0, FREQ_STANDARD = 1 };
 
 // Device-resident scalars of the conjugate-gradient loop (FP64).
 //

@@ -227,12 +227,21 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     // modified frequency vector of the rotated scheme (eq. A.4):
     // k_i = 1/4 (-i)(E_i - 1) prod_{j != i} (1 + E_j)
     const cplx<double> ex = Ex[kx], ey = Ey[ky], ez = Ez[kz];
-    const cplx<double> px = cmk(1.0 + ex.x, ex.y), py = cmk(1.0 + ey.x, ey.y), pz = cmk(1.0 + ez.x, ez.y);
-    const cplx<double> mx = cmk(ex.x - 1.0, ex.y), my = cmk(ey.x - 1.0, ey.y), mz = cmk(ez.x - 1.0, ez.y);
     cplx<double> kv[3];
-    kv[0] = cmuli(cscale(cmul(mx, cmul(py, pz)), 0.25), -1.0);
-    kv[1] = cmuli(cscale(cmul(my, cmul(px, pz)), 0.25), -1.0);
-    kv[2] = cmuli(cscale(cmul(mz, cmul(px, py)), 0.25), -1.0);
+    if (g.freq == FREQ_STANDARD) {
+      // xi = arg(E) in (-pi, pi]; the Nyquist angle pi (E = -1, exact in the tables) has no
+      // derivative
+      const cplx<double> e3[3] = {ex, ey, ez};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        kv[d] = cmk((e3[d].x == -1.0 && e3[d].y == 0.0) ? 0.0 : atan2(e3[d].y, e3[d].x), 0.0);
+    } else {
+      const cplx<double> px = cmk(1.0 + ex.x, ex.y), py = cmk(1.0 + ey.x, ey.y), pz = cmk(1.0 + ez.x, ez.y);
+      const cplx<double> mx = cmk(ex.x - 1.0, ex.y), my = cmk(ey.x - 1.0, ey.y), mz = cmk(ez.x - 1.0, ez.y);
+      kv[0] = cmuli(cscale(cmul(mx, cmul(py, pz)), 0.25), -1.0);
+      kv[1] = cmuli(cscale(cmul(my, cmul(px, pz)), 0.25), -1.0);
+      kv[2] = cmuli(cscale(cmul(mz, cmul(px, py)), 0.25), -1.0);
+    }
     const bool dc = kx == 0 && ky == 0 && kz == 0;
     const double k2 = kv[0].x * kv[0].x + kv[0].y * kv[0].y + kv[1].x * kv[1].x + kv[1].y * kv[1].y +
                       kv[2].x * kv[2].x + kv[2].y * kv[2].y;

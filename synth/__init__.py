@@ -96,6 +96,81 @@ def periodic_voronoi(n: Sequence[int], centers: np.ndarray) -> np.ndarray:
     return out
 
 
+def power_cells(n: Sequence[int], centers: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """Grain id per voxel, shape (nz, ny, nx): the periodic power (Laguerre) tessellation that
+    assigns a voxel centre x to the grain minimising |x - c_g|^2 - w_g (minimum image; lowest
+    id on ties).  Equal weights give the Voronoi tessellation of periodic_voronoi."""
+    nx, ny, nz = int(n[0]), int(n[1]), int(n[2])
+    out = np.empty((nz, ny, nx), dtype=np.int32)
+    xs = np.arange(nx) + 0.5
+    ys = np.arange(ny) + 0.5
+
+    def wrap(d, L):
+        d = np.abs(d)
+        return np.minimum(d, L - d)
+
+    dx = wrap(xs[None, :] - centers[:, 0:1], nx) ** 2
+    dy = wrap(ys[None, :] - centers[:, 1:2], ny) ** 2
+    w = np.asarray(weights, dtype=np.float64)
+    for k in range(nz):
+        dz = wrap((k + 0.5) - centers[:, 2], nz) ** 2 - w
+        d2 = dz[:, None, None] + dy[:, :, None] + dx[:, None, :]
+        out[k] = np.argmin(d2, axis=0).astype(np.int32)
+    return out
+
+
+def _periodic_centroids(gid: np.ndarray, n_grains: int) -> np.ndarray:
+    """Centroid of every grain on the periodic box (per axis, the mean of the voxel-centre
+    angles 2 pi x / L mapped back to a coordinate), (x, y, z) per row; empty grains give 0."""
+    nz, ny, nx = gid.shape
+    ids = gid.reshape(-1)
+    out = np.zeros((n_grains, 3))
+    axes = ((np.arange(nx) + 0.5)[None, None, :], (np.arange(ny) + 0.5)[None, :, None],
+            (np.arange(nz) + 0.5)[:, None, None])
+    for d, (c, L) in enumerate(zip(axes, (nx, ny, nz))):
+        ang = np.broadcast_to(2.0 * math.pi * c / L, gid.shape).reshape(-1)
+        s = np.bincount(ids, np.sin(ang), n_grains)
+        co = np.bincount(ids, np.cos(ang), n_grains)
+        out[:, d] = (np.arctan2(s, co) % (2.0 * math.pi)) * L / (2.0 * math.pi)
+    return out
+
+
+def lognormal_grains(seed: int, n: Sequence[int], n_grains: int, sd_frac: float = 0.2, sweeps: int = 20):
+    """Periodic equiaxed grains whose equivalent-sphere diameters follow a lognormal
+    distribution with standard deviation sd_frac times the mean (Section 2.2 describes such
+    RVEs, made with Dream3D, which is not available here).
+
+    Target diameters are drawn lognormal (Box-Muller normals from SplitMix64) and scaled so that
+    their spheres fill the box; centres start uniform.  The cells form a periodic power
+    (Laguerre) tessellation, relaxed over a few sweeps: every non-empty cell's centre moves to
+    its centroid (which keeps the grains equiaxed) and its weight grows by (D_target^2 -
+    D^2) / 4, D the current equivalent diameter (which drives the cell volumes to their
+    targets; 20 sweeps bring every diameter within about 2 % of its target at 75^3 with 100
+    grains).  Returns (grain id per voxel (nz, ny, nx), centres, target diameters in voxels)."""
+    rng = SplitMix64(seed)
+    centers = grain_centers(rng, n_grains, n)
+    z = gaussian_noise(seed + 7919, n_grains)
+    s2 = math.log(1.0 + sd_frac ** 2)
+    d = np.exp(math.sqrt(s2) * z - 0.5 * s2)                      # mean 1, sd sd_frac
+    vol = float(n[0] * n[1] * n[2])
+    d *= (6.0 * vol / (math.pi * np.sum(d ** 3))) ** (1.0 / 3.0)  # spheres fill the box
+    w = np.zeros(n_grains)
+    gid = power_cells(n, centers, w)
+    for _ in range(sweeps):
+        d_now = equivalent_diameters(gid, n_grains)
+        full = d_now > 0
+        centers[full] = _periodic_centroids(gid, n_grains)[full]
+        w += 0.25 * (d ** 2 - d_now ** 2)
+        gid = power_cells(n, centers, w)
+    return gid, centers, d
+
+
+def equivalent_diameters(gid: np.ndarray, n_grains: int) -> np.ndarray:
+    """Equivalent-sphere diameter (voxels) of every grain of a grain map."""
+    counts = np.bincount(gid.reshape(-1), minlength=n_grains).astype(np.float64)
+    return (6.0 * counts / math.pi) ** (1.0 / 3.0)
+
+
 # --------------------------------------------------------------------------------------
 # Materials.  Elastic constants in Pa, lengths in m.
 # --------------------------------------------------------------------------------------
@@ -168,6 +243,7 @@ class RVE:
     quats: np.ndarray        # (n_grains, 4) (w, x, y, z), crystal -> sample
     material: Material
     seed: int = 0
+    grain_elastic: np.ndarray = None  # (n_grains, 3) C11, C12, C44 per grain (Pa); None: the material's
 
     @property
     def n_grains(self) -> int:
@@ -227,6 +303,37 @@ def uniaxial_tension(strain_max: float, n_inc: int, rate: float) -> LoadPath:
     return LoadPath(F_bar=F, P_bar=np.zeros((n_inc + 1, 9)), mask=UNIAXIAL_MASK.copy(), dt=dt)
 
 
+# Simple shear in the x-y plane: F-controlled shears (F_12 = rate t, the others 0), normal
+# stresses P_11 = P_22 = P_33 = 0.
+SHEAR_MASK = np.array([0, 1, 1, 1, 0, 1, 1, 1, 0], dtype=np.uint8)
+# Equibiaxial tension in x and y: F_11 = F_22 = 1 + rate t, shears held at 0, P_33 = 0.
+BIAXIAL_MASK = np.array([1, 1, 1, 1, 1, 1, 1, 1, 0], dtype=np.uint8)
+# Stress-controlled shear: P_12 prescribed (a ramp), P_11 = P_22 = P_33 = 0, the other shears of F
+# held at 0 (F_12 follows from equilibrium).
+STRESS_SHEAR_MASK = np.array([0, 0, 1, 1, 0, 1, 1, 1, 0], dtype=np.uint8)
+
+
+def simple_shear(gamma_max: float, n_inc: int, rate: float) -> LoadPath:
+    dt = gamma_max / (n_inc * rate)
+    F = np.tile(np.eye(3).reshape(9), (n_inc + 1, 1))
+    F[:, 1] = rate * dt * np.arange(n_inc + 1)
+    return LoadPath(F_bar=F, P_bar=np.zeros((n_inc + 1, 9)), mask=SHEAR_MASK.copy(), dt=dt)
+
+
+def biaxial_tension(strain_max: float, n_inc: int, rate: float) -> LoadPath:
+    dt = strain_max / (n_inc * rate)
+    F = np.tile(np.eye(3).reshape(9), (n_inc + 1, 1))
+    F[:, 0] = F[:, 4] = 1.0 + rate * dt * np.arange(n_inc + 1)
+    return LoadPath(F_bar=F, P_bar=np.zeros((n_inc + 1, 9)), mask=BIAXIAL_MASK.copy(), dt=dt)
+
+
+def stress_controlled_shear(tau_max: float, n_inc: int, dt: float) -> LoadPath:
+    P = np.zeros((n_inc + 1, 9))
+    P[:, 1] = tau_max * np.arange(n_inc + 1) / n_inc
+    return LoadPath(F_bar=np.tile(np.eye(3).reshape(9), (n_inc + 1, 1)), P_bar=P,
+                    mask=STRESS_SHEAR_MASK.copy(), dt=dt)
+
+
 # --------------------------------------------------------------------------------------
 # The benchmark workloads
 # --------------------------------------------------------------------------------------
@@ -248,6 +355,8 @@ def workload(name: str, n_override=None, n_inc_override=None):
     sweep32:  32 RVEs of uneven size (32^3..96^3), 16..128 grains, d log-uniform in
               [10, 200] um, Cu/Ag/Ni, 3% in 30 increments at 1e-4/s (a grain-size sweep).
     cu64g100: 64^3, 100 grains, Cu, d = 30 um, 4% in 40 increments at 1e-4/s.
+    paper75:  75^3 (3 x 5^2), 100 equiaxed grains with lognormal equivalent diameters (sd 20 %
+              of the mean), mean equivalent diameter 20 um, Cu, rho_i = 1.2e12, 5% in 50 at 1e-4/s.
     """
     if name == "cu16":
         n = n_override or 16
@@ -280,6 +389,15 @@ def workload(name: str, n_override=None, n_inc_override=None):
             rves.append(RVE(n=(nr, nr, nr), voxel_size=voxel_size_for(d, ng, nr),
                             grain_of_voxel=gid, quats=quats, material=mat, seed=1040 + r))
         path = uniaxial_tension(0.03, n_inc_override or 30, 1e-4)
+    elif name == "paper75":
+        n = n_override or 75
+        mat = material("Cu", rho0=1e11, c_gnd=1.0)
+        gid, _, _ = lognormal_grains(106, (n, n, n), 100)
+        quats = shoemake_quaternions(SplitMix64(1106), 100)
+        d_vox = float(np.mean(equivalent_diameters(gid, 100)))
+        rves = [RVE(n=(n, n, n), voxel_size=20e-6 / d_vox, grain_of_voxel=gid, quats=quats, material=mat,
+                    seed=106)]
+        path = uniaxial_tension(0.05, n_inc_override or 50, 1e-4)
     elif name == "cu64g100":
         n = n_override or 64
         mat = material("Cu", rho0=1e11, c_gnd=1.0)
@@ -288,6 +406,66 @@ def workload(name: str, n_override=None, n_inc_override=None):
     else:
         raise ValueError(name)
     return rves, path
+
+
+HALL_PETCH_MATERIALS = ("Cu", "Al", "Ag", "Ni")
+HALL_PETCH_SIZES = (10e-6, 20e-6, 40e-6, 80e-6)
+
+
+def hall_petch_workload(n: int = 32, n_grains: int = 100, strain_max: float = 0.05, n_inc: int = 50,
+                        materials=HALL_PETCH_MATERIALS, sizes=HALL_PETCH_SIZES, seed: int = 107):
+    """The grain-size study of Section 3: for each material (workload elastic constants, Table 2
+    dislocation parameters, the annealed initial density 1e11 per system, i.e. rho_i = 1.2e12),
+    one periodic RVE of n^3 voxels with n_grains equiaxed lognormal grains (sd 20 % of the mean)
+    scaled to the mean equivalent diameters in sizes (the voxel size follows), plus its twin
+    without the GND term (c_gnd = 0, the paper's "infinite" grain size, whose response does not
+    depend on the size).  Tension to strain_max in n_inc increments at 1e-4/s.  Returns (RVEs,
+    load path, labels (material, size or None for the twin))."""
+    gid, _, _ = lognormal_grains(seed, (n, n, n), n_grains)
+    d_vox = float(np.mean(equivalent_diameters(gid, n_grains)))
+    rves, labels = [], []
+    for m_i, name in enumerate(materials):
+        quats = shoemake_quaternions(SplitMix64(seed + 1000 + m_i), n_grains)
+        for D in list(sizes) + [None]:
+            mat = material(name, rho0=1e11, c_gnd=0.0 if D is None else 1.0)
+            h = (sizes[0] if D is None else D) / d_vox
+            rves.append(RVE(n=(n, n, n), voxel_size=h, grain_of_voxel=gid, quats=quats, material=mat, seed=seed))
+            labels.append((name, D))
+    return rves, uniaxial_tension(strain_max, n_inc, 1e-4), labels
+
+
+def beam_cell(n_beam: int = 200, n_clamp: int = 16, n_depth: int = 10, n_soft: int = 10, length: float = 10.0,
+              E: float = 200e9, ratio: float = 1000.0, nz: int = 1):
+    """The elastic beam benchmark of Appendix B as a periodic cell (x along the beam, y across):
+    a beam of length L = `length` and depth L / 20 (n_beam x n_depth voxels), clamped at both
+    ends by a stiff column (n_clamp voxels wide, the whole height) and bounded above and below by
+    soft layers of n_soft voxels each, which stand in for free surfaces.  Three isotropic phases
+    with Poisson ratio 0 (C11 = E, C12 = 0, C44 = E / 2; with no Poisson coupling the plane-stress
+    and plane-strain answers coincide): grain 0 the clamp (ratio x E), grain 1 the beam (E),
+    grain 2 the soft layers (E / ratio).  Elastic: tau0 = 1e20 Pa and no hardening, so no slip.
+    The load shears the cell by F_21 = delta / L_cell, which moves one clamp by delta = L / 1000
+    against the other (beam ends held parallel); F_12 = F_13 = F_23 = F_31 = F_32 = 0 and F_33 = 1
+    are prescribed (with F_12 free the cell would rotate instead of bending the beam) and
+    P_11 = P_22 = 0.  Returns (RVE, one-increment load path, geometry)."""
+    nx, ny = n_clamp + n_beam, 2 * n_soft + n_depth
+    h = length / n_beam
+    gid = np.full((nz, ny, nx), 2, dtype=np.int32)
+    gid[:, n_soft:n_soft + n_depth, :] = 1
+    gid[:, :, :n_clamp] = 0
+    ge = np.array([[ratio * E, 0.0, ratio * E / 2], [E, 0.0, E / 2], [E / ratio, 0.0, E / (2 * ratio)]])
+    mat = Material(C11=E, C12=0.0, C44=E / 2, burgers=2.5e-10, y_c=1.5e-8, K_sim=6.0, tau0=1e20, c_gnd=0.0,
+                   hardening=0)
+    quats = np.tile([1.0, 0.0, 0.0, 0.0], (3, 1))
+    rve = RVE(n=(nx, ny, nz), voxel_size=h, grain_of_voxel=gid, quats=quats, material=mat, seed=0,
+              grain_elastic=ge)
+    delta = length / 1000.0
+    F = np.tile(np.eye(3).reshape(9), (2, 1))
+    F[1, 3] = delta / (nx * h)
+    mask = np.array([0, 1, 1, 1, 0, 1, 1, 1, 1], dtype=np.uint8)
+    path = LoadPath(F_bar=F, P_bar=np.zeros((2, 9)), mask=mask, dt=1.0)
+    geom = {"n_clamp": n_clamp, "n_beam": n_beam, "n_depth": n_depth, "n_soft": n_soft, "h": h,
+            "length": length, "delta": delta}
+    return rve, path, geom
 
 
 def random_deformations(seed: int, count: int, amplitude: float) -> np.ndarray:

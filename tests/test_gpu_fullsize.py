@@ -1,7 +1,8 @@
 """Parity at the benchmark workloads' full sizes in the launch configuration the benchmark
 times (mixed precision, performance tolerances): cu64 (64^3, 64 grains, strain-gradient
-Cu), al128 (128^3, 200 grains, Al), cu64g100 (64^3, 100 grains) and sweep32 (32 RVEs of
-uneven size in one handle; five of them are checked).  The oracle cannot run a whole
+Cu), al128 (128^3, 200 grains, Al), cu64g100 (64^3, 100 grains), sweep32 (32 RVEs of
+uneven size in one handle; five of them are checked) and paper75 (the paper's geometry:
+75^3 = 3 x 5^2 voxels, radix-3 and radix-5 transforms, 100 lognormal equiaxed grains).  The oracle cannot run a whole
 increment at these sizes, so it checks sampled outputs one by one and properties that hold
 at any size (GPU only)."""
 import numpy as np
@@ -21,7 +22,7 @@ def _checked(rves):
     return sorted({i for i in pick if i < len(rves)})
 
 
-@pytest.fixture(scope="module", params=["cu64", "al128", "cu64g100", "sweep32"])
+@pytest.fixture(scope="module", params=["cu64", "al128", "cu64g100", "sweep32", "paper75"])
 def run(request):
     import torch
     if not torch.cuda.is_available():

@@ -375,3 +375,103 @@ def test_adjoint_solve_refuses_a_tangent_that_is_not_the_committed_increments(li
         h2.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)   # fails (RVE_ENOCONV)
     with pytest.raises(lib.RVEError):
         h2.adjoint_solve(g, path.mask, g.clone())
+
+
+def test_lognormal_grains_on_a_radix_3_and_5_grid_fp64_match_oracle(lib):
+    """The paper's kind of microstructure (equiaxed grains with lognormal sizes, Section 2.2)
+    on a 15^3 = 3 x 5 grid (radix-3 and radix-5 transforms on every axis), two increments of
+    the strain-gradient Cu workload in FP64: <P> to the 1e-10 bar, and the Nye and GND fields."""
+    gid, _, _ = synth.lognormal_grains(21, (15, 15, 15), 12)
+    quats = synth.shoemake_quaternions(synth.SplitMix64(1021), 12)
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    rve = synth.RVE(n=(15, 15, 15), voxel_size=1.5e-6, grain_of_voxel=gid, quats=quats, material=mat, seed=21)
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    o, h, out = _run_both(lib, rve, path, 2, newton_tol=1e-12, cg_tol=1e-11)
+    for Po, Pg, Fo, Fg in out:
+        print("  <P> difference", np.max(np.abs(Pg - Po)) / np.abs(Po).max(), flush=True)
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
+    _check_gnd_fields(h, o, rve)
+
+
+@pytest.mark.parametrize("load", ["shear", "biaxial", "stress_shear"])
+def test_general_mixed_control_fp64_matches_oracle(lib, load):
+    """Mixed control beyond uniaxial tension (eq. 15 and the zero-frequency rule): simple shear
+    (normal stresses free), equibiaxial tension (P_33 free) and a stress-controlled shear (a
+    prescribed nonzero P_12 with F_12 free), two increments of the strain-gradient Cu workload
+    at 8^3 in FP64 against the oracle: <P> and <F> to the 1e-10 bar, and the prescribed
+    averages met."""
+    rves, _ = synth.workload("cu64", n_override=8)
+    path = {"shear": lambda: synth.simple_shear(0.01, 10, 1e-4),
+            "biaxial": lambda: synth.biaxial_tension(0.005, 10, 1e-4),
+            "stress_shear": lambda: synth.stress_controlled_shear(20e6, 10, 10.0)}[load]()
+    o, h, out = _run_both(lib, rves[0], path, 2)
+    for k, (Po, Pg, Fo, Fg) in enumerate(out, start=1):
+        scale = np.abs(Po).max()
+        print(f"  {load} increment {k}: <P> difference {np.max(np.abs(Pg - Po)) / scale:.2e}", flush=True)
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * scale
+        assert np.max(np.abs(Fg - Fo)) <= 1e-11
+        free = path.mask == 0
+        assert np.max(np.abs(Pg[free] - path.P_bar[k][free])) <= 1e-8 * scale
+        fixed = path.mask == 1
+        assert np.max(np.abs(Fg[fixed] - path.F_bar[k][fixed])) <= 1e-12
+
+
+def test_time_step_cutback_equals_explicit_half_increments(lib):
+    """With max_cutbacks, an increment that fails is committed as two increments of half the
+    time step (targets at the midpoint, then at the end).  Here the Newton iteration budget is
+    set to what each half needs, so that a double-size increment fails directly; with one level
+    of cut-back the handle commits it in two halves, bit-identical to two explicit increments."""
+    rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
+    opts = dict(precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8, max_continuation=1)
+    b = lib.Homogenizer(rves, max_newton=40, **opts)
+    need = 0
+    # the midpoint target exactly as the library forms it: (previous target + target) / 2
+    F_mid = 0.5 * (path.F_bar[0] + path.F_bar[2])
+    P_mid = 0.5 * (path.P_bar[0] + path.P_bar[2])
+    for F_t, P_t in ((F_mid, P_mid), (path.F_bar[2], path.P_bar[2])):
+        need = max(need, b.step(F_t, path.mask, P_t, path.dt)[0]["newton_iters"])
+    ref = {n: b.field(n) for n in ("F", "P", "Fp", "rho_ssd", "rho_gnd", "dg")}
+    P_ref = b.macro()[0]
+    print("Newton iterations of the larger half", need, flush=True)
+    plain = lib.Homogenizer(rves, max_newton=need, **opts)
+    with pytest.raises(lib.RVEError):
+        plain.step(path.F_bar[2], path.mask, path.P_bar[2], 2 * path.dt)
+    a = lib.Homogenizer(rves, max_newton=need, max_cutbacks=1, **opts)
+    st = a.step(path.F_bar[2], path.mask, path.P_bar[2], 2 * path.dt)[0]
+    print("cut-back stats", st, flush=True)
+    assert st["cutbacks"] == 1 and st["status"] == 0
+    assert st["discarded_voxel_iterations"] > 0
+    for n, v in ref.items():
+        assert np.array_equal(a.field(n), v), n
+    assert np.array_equal(a.macro()[0], P_ref)
+
+
+def test_cu16_whole_curve_matches_the_oracle_reference():
+    """The 16^3 FP64 workload (8 grains, Cu, tau0 = 10 MPa, no gradient term) through all 20
+    increments to 1 %: <P> and <F> after every increment against the oracle's curve stored in
+    tests/golden/c1_cu16_curve.json (written by tests/golden/make_c1_curve.py, which calls only
+    the oracle, at the same tolerances): the 1e-10 bar at every increment."""
+    import json
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01946_amd as m
+    m.lib()
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_cu16_curve.json")) as f:
+        ref = json.load(f)
+    rves, path = synth.workload("cu16")
+    h = m.Homogenizer(rves, precision=m.RVE_FP64, newton_tol=ref["newton_tol"], cg_tol=ref["cg_tol"],
+                      max_cg=20000, max_newton=80)
+    worst = 0.0
+    scale = np.abs(np.array(ref["P_avg"])).max()
+    for k in range(1, path.n_inc + 1):
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        Pg, Fg, _ = h.macro()
+        d = np.max(np.abs(Pg - np.array(ref["P_avg"][k - 1]))) / scale
+        worst = max(worst, d)
+        print(f"increment {k}: <P>_11 {Pg[0]:.10e} reference {ref['P_avg'][k - 1][0]:.10e} difference {d:.2e}",
+              flush=True)
+        assert d <= 1e-10
+        assert np.max(np.abs(Fg - np.array(ref["F_avg"][k - 1]))) <= 1e-12
+    print("largest difference over the curve", worst, flush=True)

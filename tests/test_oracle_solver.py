@@ -7,11 +7,20 @@ import synth
 from oracle import elasticity, nye, reference, solver, spectral
 
 
-def test_homogeneous_single_grain_equals_material_point():
+@pytest.mark.parametrize("load", ["uniaxial", "shear", "biaxial", "stress_shear"])
+def test_homogeneous_single_grain_equals_material_point(load):
+    """One grain: every voxel carries the 0-D mixed-control material-point solution (solved
+    directly on the free macroscopic components), for uniaxial tension, simple shear,
+    equibiaxial tension and a stress-controlled shear (a nonzero prescribed P_12): the
+    zero-frequency rule of the projection (keep the stress-controlled averages minus their
+    targets, drop the deformation-controlled ones) is pinned by a solve that does not use it."""
     mat = synth.material("Cu", tau0=10e6, c_gnd=1.0)
     q = synth.shoemake_quaternions(synth.SplitMix64(21), 1)[0]
     rve = synth.single_crystal_rve((2, 3, 2), q, mat)
-    path = synth.uniaxial_tension(0.004, 4, 1e-3)
+    path = {"uniaxial": lambda: synth.uniaxial_tension(0.004, 4, 1e-3),
+            "shear": lambda: synth.simple_shear(0.006, 4, 1e-3),
+            "biaxial": lambda: synth.biaxial_tension(0.003, 4, 1e-3),
+            "stress_shear": lambda: synth.stress_controlled_shear(12e6, 4, 1.0)}[load]()
     s = solver.RVESolver(rve)
     recs = s.run(path)
     ref = reference.material_point_path(mat, q, path)
