@@ -313,6 +313,21 @@ int32_t rve_density_sensitivity(const rve_material* mat, int64_t nvox, const dou
 int32_t rve_project(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
                     const double* dc_target, double* out, void* stream);
 
+/* rve_project for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same projection with
+ * the same kernels, but the half spectrum and the root tables live in one fixed device array
+ * of the library, 64 MiB per device, held from the first call on a device until the process
+ * ends.  The call allocates nothing: it fills the root tables and runs the projection on
+ * stream (or the null stream) and returns once the work is queued (no synchronisation).
+ * Limit: the spectrum, 9 x (n0/2 + 1) x n1 x n2 complex values of 16 bytes (RVE_FP64) or 8
+ * bytes (RVE_MIXED), must fit in 64 MiB - 64 KiB (for instance 96^3 in FP64, 112^3 in FP32);
+ * a larger grid is rejected with RVE_EINVAL before any device work.  Every call on a device
+ * shares that device's array and leaves its contents behind: calls that overlap in time on
+ * one device (different streams or threads) race and must be serialised by the caller.
+ * Arguments, layouts and other errors as for rve_project. */
+int32_t rve_project_noalloc(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
+                            const double* dc_target, double* out, void* stream);
+
 /* Nye tensor alpha_ij = eps_jml d_m Fp_il (eq. 12 with the rotated-scheme derivative of
  * Appendix A and voxel size h; device in/out, 9 x nvox) and, when gid/grain_quat are
  * given, the GND densities per slip system (eq. 13; device out, 12 x nvox). */

@@ -16,6 +16,7 @@ from ._lib import (RVE_FP64, RVE_MIXED, LibraryMissing, RVEError, check, lib, rv
                    rve_options, rve_step_stats)
 
 __all__ = ["RVE_FP64", "RVE_MIXED", "Homogenizer", "make_material", "constitutive_batch", "project",
+           "project_noalloc",
            "spectral_curl", "gnd_adjoint", "stress_sensitivity", "stress_sensitivity_vjp",
            "density_sensitivity",
            "LibraryMissing", "RVEError", "lib"]
@@ -218,6 +219,16 @@ def project(n, A, mask, out, dc_target=None, precision=RVE_FP64, stream=None):
     dc = None if dc_target is None else np.ascontiguousarray(np.asarray(dc_target, float).reshape(9))
     check(lib().rve_project(nn, precision, _ptr(A), m.ctypes.data_as(C.POINTER(C.c_uint8)),
                             _dp(dc) if dc is not None else None, _ptr(out), _stream(stream)))
+
+
+def project_noalloc(n, A, mask, out, dc_target=None, precision=RVE_FP64, stream=None):
+    """rve_project_noalloc: the projection with the library's fixed scratch array (no device
+    allocation; asynchronous on stream)."""
+    nn = (C.c_int32 * 3)(*[int(v) for v in n])
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(9))
+    dc = None if dc_target is None else np.ascontiguousarray(np.asarray(dc_target, float).reshape(9))
+    check(lib().rve_project_noalloc(nn, precision, _ptr(A), m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                    _dp(dc) if dc is not None else None, _ptr(out), _stream(stream)))
 
 
 def spectral_curl(n, h, Fp, nye, gid=None, quats=None, burgers=0.0, rho_gnd=None, precision=RVE_FP64,

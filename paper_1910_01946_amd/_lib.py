@@ -97,6 +97,8 @@ def lib():
     L.rve_constitutive_batch.restype = C.c_int32
     L.rve_project.argtypes = [P(C.c_int32), C.c_int32, vp, P(C.c_uint8), dp, vp, vp]
     L.rve_project.restype = C.c_int32
+    L.rve_project_noalloc.argtypes = [P(C.c_int32), C.c_int32, vp, P(C.c_uint8), dp, vp, vp]
+    L.rve_project_noalloc.restype = C.c_int32
     L.rve_spectral_curl.argtypes = [P(C.c_int32), C.c_int32, C.c_double, vp, vp, vp, C.c_int32, dp,
                                     C.c_double, vp, vp]
     L.rve_spectral_curl.restype = C.c_int32
@@ -126,7 +128,7 @@ def lib():
 # names the C ABI exports (checked by the CPU test suite)
 EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress", "rve_get_field",
            "rve_state_bytes", "rve_save_state", "rve_load_state", "rve_destroy", "rve_last_error",
-           "rve_constitutive_batch", "rve_project", "rve_spectral_curl", "rve_timing_start",
+           "rve_constitutive_batch", "rve_project", "rve_project_noalloc", "rve_spectral_curl", "rve_timing_start",
            "rve_timing_read", "rve_adjoint_solve", "rve_adjoint_increment", "rve_gnd_adjoint",
            "rve_stress_sensitivity", "rve_stress_sensitivity_vjp", "rve_density_sensitivity"]
 

@@ -1439,6 +1439,70 @@ static void prepare_device() {
   done.push_back(dev);
 }
 
+// ------------------------------------------------------------------------------------
+// Projection without allocation (rve_project_noalloc)
+// ------------------------------------------------------------------------------------
+// Working memory of rve_project_noalloc: the half spectrum and the root tables, in one fixed
+// device array (each device holds its own copy until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: it takes the device address once per device
+// from hipGetSymbolAddress (noalloc_base) and uses that.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr size_t kNoAllocTables = size_t(64) << 10;  // 3 axes x (tw, E) x 256 roots x 16 B = 24 KiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static void* noalloc_base() {
+  static std::mutex mu;
+  static std::vector<std::pair<int, void*>> addr;  // (device, address of scratch there)
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& e : addr)
+    if (e.first == dev) return e.second;
+  void* p = nullptr;
+  HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(RVE_EDEVICE, "no device address for the projection scratch array");
+  addr.emplace_back(dev, p);
+  return p;
+}
+
+// Root tables of one axis of length n on the device: tw[k] = exp(-2 pi i k / n) in the
+// spectral precision T, E[q] = exp(+2 pi i q / n) in FP64, exact at the quarter turns.
+template <typename T>
+__global__ void k_root_tables(int n, T* tw, double* E) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)k / (double)n, &s, &c);
+  if (k == 0) { c = 1.0; s = 0.0; }
+  if (2 * k == n) { c = -1.0; s = 0.0; }
+  if (4 * k == n) { c = 0.0; s = 1.0; }
+  if (4 * k == 3 * n) { c = 0.0; s = -1.0; }
+  tw[2 * k] = (T)c;
+  tw[2 * k + 1] = (T)(-s);
+  E[2 * k] = c;
+  E[2 * k + 1] = s;
+}
+
+// The grid plan of rve_project_noalloc inside the scratch array: tables at base, the
+// spectrum from base + kNoAllocTables.  Throws RVE_EINVAL (before touching the device when
+// base is null) if the grid does not fit.
+static void noalloc_plan(GridPlan& g, const int n[3], bool fp32, unsigned char* base, void** spec) {
+  plan_geometry(g, n);
+  const size_t spec_bytes = tsize(fp32) * 2 * 9 * (size_t)g.nspec;
+  if (spec_bytes > kNoAllocBytes - kNoAllocTables)
+    throw Error(RVE_EINVAL, "grid too large for rve_project_noalloc: its spectrum needs " +
+                                std::to_string(spec_bytes) + " bytes, the scratch array holds " +
+                                std::to_string(kNoAllocBytes - kNoAllocTables));
+  if (!base) return;
+  const void** tw[3] = {&g.twx, &g.twy, &g.twz};
+  const void** E[3] = {&g.Ex, &g.Ey, &g.Ez};
+  for (int d = 0; d < 3; ++d) {
+    *tw[d] = base + (size_t)d * 8192;             // 256 roots x 16 B at most
+    *E[d] = base + (size_t)(3 + d) * 8192;
+  }
+  *spec = base + kNoAllocTables;
+}
+
 // The autotuner: for a grid size and spectral precision, time the z pass (z transforms and
 // the projection of eq. 17) at each candidate tile width (kx columns per block: the widest
 // that the 256-thread block holds, then halvings down to 1) and keep the fastest for the
@@ -2214,6 +2278,41 @@ int32_t rve_gnd_adjoint(const int32_t n[3], int32_t precision, double h, const d
     launch_roll_back(g.nx, g.ny, g.nz, curl.as<double>(), Fp_bar, st);
     check_launch("gnd adjoint");
     HIPCHECK(hipStreamSynchronize(st));
+    return RVE_OK;
+  });
+}
+
+int32_t rve_project_noalloc(const int32_t n[3], int32_t precision, const double* A, const uint8_t* mask,
+                            const double* dc_target, double* out, void* stream) {
+  return guarded([&]() -> int32_t {
+    if (!n || !A || !mask || !out) throw Error(RVE_EINVAL, "null argument");
+    if (precision != RVE_FP64 && precision != RVE_MIXED) throw Error(RVE_EINVAL, "unknown precision");
+    const int nn[3] = {n[0], n[1], n[2]};
+    const bool fp32 = precision == RVE_MIXED;
+    GridPlan g;
+    void* spec = nullptr;
+    noalloc_plan(g, nn, fp32, nullptr, &spec);  // shape and size checks, host only
+    prepare_device();
+    unsigned char* base = static_cast<unsigned char*>(noalloc_base());
+    noalloc_plan(g, nn, fp32, base, &spec);
+    hipStream_t st = (hipStream_t)stream;
+    const int* dims[3] = {&g.nx, &g.ny, &g.nz};
+    const void* tw[3] = {g.twx, g.twy, g.twz};
+    const void* E[3] = {g.Ex, g.Ey, g.Ez};
+    for (int d = 0; d < 3; ++d) {
+      const int m = *dims[d];
+      if (fp32)
+        hipLaunchKernelGGL(k_root_tables<float>, dim3((m + 255) / 256), dim3(256), 0, st, m,
+                           (float*)const_cast<void*>(tw[d]), (double*)const_cast<void*>(E[d]));
+      else
+        hipLaunchKernelGGL(k_root_tables<double>, dim3((m + 255) / 256), dim3(256), 0, st, m,
+                           (double*)const_cast<void*>(tw[d]), (double*)const_cast<void*>(E[d]));
+    }
+    check_launch("root tables");
+    double keep[9];
+    for (int c = 0; c < 9; ++c) keep[c] = mask[c] ? 0.0 : 1.0;
+    project_field(g, fp32, plane_enabled() && plane_fits(g, fp32), spec, A, keep, dc_target, out, st);
+    check_launch("project (no allocation)");
     return RVE_OK;
   });
 }

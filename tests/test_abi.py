@@ -81,3 +81,24 @@ def test_sensitivity_entry_points_reject_bad_arguments_before_any_device_call():
     assert L.rve_density_sensitivity(m, 0, fake, fake, fake, fake, None) == -1
     assert L.rve_density_sensitivity(ctypes.byref(bad), 8, fake, fake, fake, fake, None) == -1
     assert L.rve_last_error()
+
+
+def test_noalloc_projection_rejects_grids_beyond_its_scratch_array_on_the_host():
+    """rve_project_noalloc checks the grid against its fixed 64 MiB scratch array before any
+    device work: 128^3 in FP64 (a 153 MB spectrum) is refused with RVE_EINVAL, as are null
+    pointers and bad grid sizes; no GPU is needed to see the errors."""
+    from paper_1910_01946_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    L = _lib.lib()
+    fake = ctypes.c_void_p(16)   # never dereferenced: every call below fails its host checks
+    mask = (ctypes.c_uint8 * 9)(1, 1, 1, 1, 0, 1, 1, 1, 0)
+    big = (ctypes.c_int32 * 3)(128, 128, 128)
+    assert L.rve_project_noalloc(big, 0, fake, mask, None, fake, None) == -1
+    assert b"too large" in L.rve_last_error()
+    assert L.rve_project_noalloc(big, 1, fake, mask, None, fake, None) == -1   # 77 MB in FP32
+    odd = (ctypes.c_int32 * 3)(14, 8, 8)  # prime factor 7
+    assert L.rve_project_noalloc(odd, 0, fake, mask, None, fake, None) == -1
+    ok = (ctypes.c_int32 * 3)(8, 8, 8)
+    assert L.rve_project_noalloc(ok, 0, None, mask, None, fake, None) == -1
+    assert L.rve_project_noalloc(ok, 2, fake, mask, None, fake, None) == -1
