@@ -57,15 +57,26 @@ FAMILY_KERNELS = {
     "plane_fwd": ("k_plane_fwd", _PLANE_SRC),
     "mid": ("k_mid", _MID_SRC),
     "plane_inv": ("k_plane_inv", _PLANE_SRC),
+    "cg_grad": ("k_cg_grad", _PLANE_SRC),
+    "plane_div": ("k_plane_fwd", _PLANE_SRC),
+    "mid3": ("k_mid", _MID_SRC),
+    "plane_w": ("k_plane_inv", _PLANE_SRC),
 }
-SPECTRAL = ("cg_prep", "plane_fwd", "mid", "plane_inv")
+# the spectral families: the CG iterations (factorised projection: prep, divergence pass, z
+# pass on three components, inverse pass, gradient pass) and the nine-component passes of the
+# residual evaluations
+SPECTRAL = ("cg_prep", "plane_div", "mid3", "plane_w", "cg_grad", "plane_fwd", "mid", "plane_inv")
 # the kernel instantiation each spectral family runs in the mixed form (FP32 spectra, FP16
 # tangent copy) and in the FP64 form
 INSTANTIATION = {
     ("cg_prep", "mixed"): "k_cg_prep<float, K16=1, TR=0>", ("cg_prep", "fp64"): "k_cg_prep<double, 0, 0>",
-    ("plane_fwd", "mixed"): "k_plane_fwd<float, ...>", ("plane_fwd", "fp64"): "k_plane_fwd<double, ...>",
+    ("plane_div", "mixed"): "k_plane_fwd<float, PF_DIV, ...>", ("plane_div", "fp64"): "k_plane_fwd<double, PF_DIV, ...>",
+    ("mid3", "mixed"): "k_mid<float, MID_GREEN3, ...>", ("mid3", "fp64"): "k_mid<double, MID_GREEN3, ...>",
+    ("plane_w", "mixed"): "k_plane_inv<float, PI_OUT_T, ...>", ("plane_w", "fp64"): "k_plane_inv<double, PI_OUT_T, ...>",
+    ("cg_grad", "mixed"): "k_cg_grad<float>", ("cg_grad", "fp64"): "k_cg_grad<double>",
+    ("plane_fwd", "mixed"): "k_plane_fwd<float, PF_F64, ...>", ("plane_fwd", "fp64"): "k_plane_fwd<double, PF_F64, ...>",
     ("mid", "mixed"): "k_mid<float, MID_GREEN, ...>", ("mid", "fp64"): "k_mid<double, MID_GREEN, ...>",
-    ("plane_inv", "mixed"): "k_plane_inv<float, ...>", ("plane_inv", "fp64"): "k_plane_inv<double, ...>",
+    ("plane_inv", "mixed"): "k_plane_inv<float, PI_RESID, ...>", ("plane_inv", "fp64"): "k_plane_inv<double, PI_RESID, ...>",
 }
 NEWTON_TOL, CG_TOL = 1e-6, 1e-3
 
@@ -266,14 +277,16 @@ def roofline(fam, T, workload):
         if n == 0:
             continue
         achieved = units / (ms * 1e-3) / 1e9
-        per.append({"kernel": FAMILY_KERNELS[f][0], "instantiation": INSTANTIATION[(f, "mixed")], "launches": n,
+        per.append({"family": f, "kernel": FAMILY_KERNELS[f][0], "instantiation": INSTANTIATION[(f, "mixed")],
+                    "launches": n,
                     "avg_launch_us": 1e3 * ms / n, "algorithmic_bytes_per_launch": units / n,
                     "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "share": round(share[f], 4),
                     "traffic": stored_traffic(f, workload, "mixed")})
     dom = max(share, key=share.get)
-    out = {"kernel": FAMILY_KERNELS[dom][0], "share_of_serialised_replay": {f: round(v, 4) for f, v in share.items()}}
+    out = {"kernel": FAMILY_KERNELS[dom][0], "family": dom,
+           "share_of_serialised_replay": {f: round(v, 4) for f, v in share.items()}}
     if dom in SPECTRAL:
-        d = next(p for p in per if p["kernel"] == FAMILY_KERNELS[dom][0])
+        d = next(p for p in per if p["family"] == dom)
         out.update({"instantiation": d["instantiation"], "bound": "hbm", "achieved": d["achieved"],
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": d["traffic"],
                     "launches": d["launches"], "avg_launch_us": d["avg_launch_us"],

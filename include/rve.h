@@ -111,6 +111,13 @@ typedef struct {
                             of the trigonometric interpolant, k = xi, Nyquist derivative 0), the
                             comparison of Appendix B.  Both the projection of eq. 17 and the
                             curl of eq. 12 use the chosen scheme; the reverse pass needs 0    */
+  int32_t projection;    /* form of the projection inside the conjugate-gradient iterations:
+                            0: factorised where it applies (rotated scheme, plane path): the
+                            operator of eq. 17 as a divergence stencil, transforms of three
+                            components, 1/|k|^2 and a gradient stencil (the symbols of eq. A.4
+                            are those stencils), a third of the transforms of the nine-component
+                            form; 1: the nine-component form everywhere.  Same operator: the
+                            results differ by rounding only                                  */
 } rve_options;
 
 /* Per-RVE statistics of one increment. */
@@ -235,7 +242,11 @@ enum {
   RVE_KF_CG_PREP = 3,        /* CG vector update, r.r and K : r (eq. 18)                          */
   RVE_KF_PLANE_FWD = 4,      /* x and y forward FFTs of one component plane                      */
   RVE_KF_MID = 5,            /* z FFTs and the Green operator of eq. 17 with its inverse z FFTs  */
-  RVE_KF_PLANE_INV = 6       /* y and x inverse FFTs and the CG epilogue                          */
+  RVE_KF_PLANE_INV = 6,      /* y and x inverse FFTs and the CG epilogue                          */
+  RVE_KF_CG_GRAD = 7,        /* gradient stencil of the factorised projection and the CG epilogue */
+  RVE_KF_PLANE_DIV = 8,      /* divergence stencil and x and y forward FFTs (factorised form)     */
+  RVE_KF_MID3 = 9,           /* z FFTs and 1/|k|^2 on three components (factorised form)          */
+  RVE_KF_PLANE_W = 10        /* y and x inverse FFTs of three components (factorised form)        */
 };
 
 /* While mask != 0, every launch of the selected families during rve_step_increment

@@ -46,7 +46,7 @@ class Homogenizer:
 
     def __init__(self, rves, precision=RVE_FP64, newton_tol=1e-10, cg_tol=1e-8, max_newton=40,
                  max_cg=2000, max_backtrack=12, device=0, stream=None, use_graph=0, workers=0, autotune=0,
-                 max_cutbacks=0, max_continuation=0, frequencies=0):
+                 max_cutbacks=0, max_continuation=0, frequencies=0, projection=0):
         L = lib()
         n = len(rves)
         self._keep = []
@@ -71,7 +71,8 @@ class Homogenizer:
                           max_cg=max_cg, max_backtrack=max_backtrack, device=device,
                           stream=C.c_void_p(stream) if stream else None, use_graph=int(use_graph),
                           workers=int(workers), autotune=int(autotune), max_cutbacks=int(max_cutbacks),
-                          max_continuation=int(max_continuation), frequencies=int(frequencies))
+                          max_continuation=int(max_continuation), frequencies=int(frequencies),
+                          projection=int(projection))
         h = C.c_void_p()
         check(L.rve_create(descs, n, C.byref(opt), C.byref(h)))
         self.h = h

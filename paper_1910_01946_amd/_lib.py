@@ -32,7 +32,8 @@ class rve_options(C.Structure):
                 ("max_newton", C.c_int32), ("max_cg", C.c_int32), ("max_backtrack", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("use_graph", C.c_int32),
                 ("workers", C.c_int32), ("autotune", C.c_int32), ("max_cutbacks", C.c_int32),
-                ("max_continuation", C.c_int32), ("frequencies", C.c_int32)]
+                ("max_continuation", C.c_int32), ("frequencies", C.c_int32),
+                ("projection", C.c_int32)]
 
 
 class rve_step_stats(C.Structure):
@@ -134,7 +135,7 @@ EXPORTS = ["rve_create", "rve_step_increment", "rve_nye_gnd", "rve_macro_stress"
 
 # kernel families of rve_timing_start / rve_timing_read
 KERNEL_FAMILIES = {"slip_fast": 0, "slip_slow": 1, "stress_tangent": 2, "cg_prep": 3, "plane_fwd": 4, "mid": 5,
-                   "plane_inv": 6}
+                   "plane_inv": 6, "cg_grad": 7, "plane_div": 8, "mid3": 9, "plane_w": 10}
 
 
 class RVEError(RuntimeError):

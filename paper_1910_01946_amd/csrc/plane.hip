@@ -55,6 +55,94 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* r
 // more threads per plane (fewer points each) shorten the chain.
 constexpr int kPlaneThreads = 512;
 
+// Source of the factorised projection's forward pass: row i of the divergence stencil,
+// v_i = sum_l D_l^H y_il with D_l^H = 1/4 (S_l^-1 - 1) prod_{m != l} (1 + S_m^-1), at plane z,
+// written into the packed row pairs of A (row 2p in .x, row 2p + 1 in .y).  The z factors
+// are taken while loading planes z and z - 1,
+//   a0 = y_i0(z) + y_i0(z-1),  a1 = y_i1(z) + y_i1(z-1),  a2 = y_i2(z-1) - y_i2(z),
+// then the x factors, e = (a2 - a0)(x) + (a0 + a2)(x-1) and f = a1(x) + a1(x-1), and the y
+// factors, v = 1/4 [(e - f)(y) + (e + f)(y-1)] (periodic indices).  The sums of y_il over the
+// plane go to plane_sums for the zero-frequency term.  VPT bounds the voxels per thread.
+template <typename T, int VPT>
+__device__ __forceinline__ void plane_divergence(const GridPlan& g, const PlaneArgs& a, int i, int z, cplx<T>* A,
+                                                 cplx<T>* B, int SA, double* red) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz, npl = nx * ny;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t nv = g.nvox;
+  const int zm = (z == 0 ? nz : z) - 1;
+  const T* Y = reinterpret_cast<const T*>(a.in);
+  const T* y0 = Y + (int64_t)(3 * i) * nv, *y1 = y0 + nv, *y2 = y1 + nv;
+  const int64_t oz = (int64_t)z * npl, om = (int64_t)zm * npl;
+  // two scratch planes: a0 + a2 in A's storage, a1 in B's (each holds ny nx values of T)
+  T* Pl = reinterpret_cast<T*>(A);
+  T* Ql = reinterpret_cast<T*>(B);
+  T em[VPT], sp[VPT];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int idx = tid + u * nthr;
+    if (idx < npl) {
+      const T u0 = y0[oz + idx], u1 = y1[oz + idx], u2 = y2[oz + idx];
+      const T w0 = y0[om + idx], w1 = y1[om + idx], w2 = y2[om + idx];
+      s0 += (double)u0;
+      s1 += (double)u1;
+      s2 += (double)u2;
+      const T a0 = u0 + w0, a1 = u1 + w1, a2 = w2 - u2;
+      em[u] = a2 - a0;
+      sp[u] = a1;
+      Pl[idx] = a0 + a2;
+      Ql[idx] = a1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int idx = tid + u * nthr;
+    if (idx < npl) {
+      const int y = fdiv(idx, g.fnx), x = idx - y * nx;
+      const int xm = (x == 0 ? nx : x) - 1;
+      const T e = em[u] + Pl[y * nx + xm];
+      const T f = sp[u] + Ql[y * nx + xm];
+      em[u] = e - f;
+      sp[u] = e + f;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int idx = tid + u * nthr;
+    if (idx < npl) Ql[idx] = sp[u];
+  }
+  __syncthreads();
+  const T quarter = (T)0.25;
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int idx = tid + u * nthr;
+    if (idx < npl) {
+      const int y = fdiv(idx, g.fnx), x = idx - y * nx;
+      const int ym = (y == 0 ? ny : y) - 1;
+      const T v = quarter * (em[u] + Ql[ym * nx + x]);
+      cplx<T>& e = A[(y >> 1) * SA + padded(x)];
+      if (y & 1) e.y = v;
+      else e.x = v;
+    }
+  }
+  // an odd row count leaves the imaginary half of the last pair unset
+  if (ny & 1)
+    for (int x = tid; x < nx; x += nthr) A[(ny >> 1) * SA + padded(x)].y = (T)0;
+  // plane sums (every thread takes part in the three reductions)
+  const double t0 = block_sum2(s0, red);
+  __syncthreads();
+  const double t1 = block_sum2(s1, red);
+  __syncthreads();
+  const double t2 = block_sum2(s2, red);
+  if (tid == 0) {
+    a.plane_sums[(3 * i + 0) * nz + z] = t0;
+    a.plane_sums[(3 * i + 1) * nz + z] = t1;
+    a.plane_sums[(3 * i + 2) * nz + z] = t2;
+  }
+}
+
 template <typename T, int SRC, int PPT, int RS>
 __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, CGState* cg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -83,6 +171,9 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
   const int tid = threadIdx.x, nthr = blockDim.x;
   load_twiddles(twx, g.twx, nx);
   load_twiddles(twy, g.twy, ny);
+  if constexpr (SRC == PF_DIV) {
+    plane_divergence<T, 2 * PPT>(g, a, c, z, A, B, SA, red);
+  } else {
   // 8 independent loads in flight per thread before the LDS writes
   const int nload = 2 * npair * nx;
   for (int b0 = tid; b0 < nload; b0 += 8 * nthr) {
@@ -109,6 +200,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
       }
     }
   }
+  }
   __syncthreads();
   fft_lines<T, PPT, RS>(A, LineLayout{npair, 1, SA, 0, 0}, g.ax, twx, (T)-1);
   for (int idx = tid; idx < npair * nxh; idx += nthr) {
@@ -134,6 +226,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[8];
   if (MODE == PI_CG && a.cg->done) return;
+  if (MODE == PI_OUT_T && a.cg && a.cg->done) return;
   const int c = blockIdx.x, z = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
   // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded());
@@ -218,6 +311,8 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
         reinterpret_cast<T*>(a.q)[o] = qv;
         reinterpret_cast<T*>(a.p)[o] = pv;
         acc += (double)pv * (double)qv;
+      } else if (MODE == PI_OUT_T) {
+        reinterpret_cast<T*>(a.out)[o] = (T)w[u];
       } else if (MODE == PI_RESID) {
         const T rv = (T)(-w[u]);
         reinterpret_cast<T*>(a.r)[o] = rv;
@@ -233,6 +328,91 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneIn
     const double s = block_sum2(acc, red);
     if (tid == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
+  if (MODE == PI_OUT_T && z == 0) {
+    // zero-frequency term of row c from the plane sums of the forward pass
+    for (int l = 0; l < 3; ++l) {
+      const int cc = 3 * c + l;
+      const double s = sum_partials(a.plane_sums + (int64_t)cc * nz, nz, red);
+      if (tid == 0) a.dc[cc] = a.mask_keep[cc] * s * a.inv_n;
+    }
+  }
+}
+
+// Gradient stencil of the factorised projection and the CG epilogue (see GradArgs):
+//   q_ij = D_j w_i + dc_ij,  D_j = 1/4 (S_j - 1) prod_{m != j} (1 + S_m),
+// from the eight corners x + {0,1}^3 of each voxel (periodic), then q = q + beta q_prev,
+// p = r + beta p and the per-block p.q.  Grid: (blocks over the ny nx columns, z chunks).
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
+  __shared__ double red[8];
+  const CGState* cg = a.cg;
+  if (cg->done) return;
+  const double beta = cg->beta;
+  const bool first = cg->iter == 0;
+  const int nx = g.nx, ny = g.ny, nz = g.nz, npl = nx * ny;
+  const int64_t nv = g.nvox;
+  const T* W = reinterpret_cast<const T*>(a.w);
+  const T* Rr = reinterpret_cast<const T*>(a.r);
+  T* P = reinterpret_cast<T*>(a.p);
+  T* Q = reinterpret_cast<T*>(a.q);
+  double dc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) dc[c] = a.dc[c];
+  const int z0 = blockIdx.y * a.lz, z1 = min(z0 + a.lz, nz);
+  double acc = 0.0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < npl; idx += gridDim.x * blockDim.x) {
+    const int y = fdiv(idx, g.fnx), x = idx - y * nx;
+    const int x1 = x + 1 == nx ? 0 : x + 1, y1 = y + 1 == ny ? 0 : y + 1;
+    // corner offsets within a plane: (y, x), (y, x+1), (y+1, x), (y+1, x+1)
+    const int off[4] = {y * nx + x, y * nx + x1, y1 * nx + x, y1 * nx + x1};
+    double lo[3][4], hi[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) lo[i][k] = (double)W[i * nv + (int64_t)z0 * npl + off[k]];
+    for (int z = z0; z < z1; ++z) {
+      const int zp = z + 1 == nz ? 0 : z + 1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hi[i][k] = (double)W[i * nv + (int64_t)zp * npl + off[k]];
+      const int64_t o = (int64_t)z * npl + idx;
+      double qn[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        qn[3 * i + 0] = 0.25 * ((lo[i][1] - lo[i][0]) + (lo[i][3] - lo[i][2]) + (hi[i][1] - hi[i][0]) +
+                                (hi[i][3] - hi[i][2]));
+        qn[3 * i + 1] = 0.25 * ((lo[i][2] - lo[i][0]) + (lo[i][3] - lo[i][1]) + (hi[i][2] - hi[i][0]) +
+                                (hi[i][3] - hi[i][1]));
+        qn[3 * i + 2] = 0.25 * ((hi[i][0] - lo[i][0]) + (hi[i][1] - lo[i][1]) + (hi[i][2] - lo[i][2]) +
+                                (hi[i][3] - lo[i][3]));
+      }
+      T r0[9], q0[9], p0[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        r0[c] = Rr[c * nv + o];
+        if (!first) {
+          q0[c] = Q[c * nv + o];
+          p0[c] = P[c * nv + o];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const double w = qn[c] + dc[c];
+        const T qv = first ? (T)w : (T)(w + beta * (double)q0[c]);
+        const T pv = first ? r0[c] : (T)((double)r0[c] + beta * (double)p0[c]);
+        Q[c * nv + o] = qv;
+        P[c * nv + o] = pv;
+        acc += (double)pv * (double)qv;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lo[i][k] = hi[i][k];
+    }
+  }
+  const double s = block_sum2(acc, red);
+  if (threadIdx.x == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // xb = x over the grid-stride range of this thread
@@ -401,6 +581,10 @@ static hipError_t plane_limits_rs(int bytes) {
   if ((f = lds_limit(k_plane_inv<T, PI_CG, PPT, RS>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_plane_inv<T, PI_RESID, PPT, RS>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_plane_inv<T, PI_OUT64, PPT, RS>, bytes)) != hipSuccess) e = f;
+  if constexpr (PPT <= 17) {
+    if ((f = lds_limit(k_plane_fwd<T, PF_DIV, PPT, RS>, bytes)) != hipSuccess) e = f;
+    if ((f = lds_limit(k_plane_inv<T, PI_OUT_T, PPT, RS>, bytes)) != hipSuccess) e = f;
+  }
   return e;
 }
 
@@ -439,7 +623,8 @@ static int plane_radix_set(const GridPlan& g) { return radix_set_for(radix_bits(
 template <typename T, int SRC, int PPT, int RS>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a, cg);
+  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(SRC == PF_DIV ? 3 : 9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g,
+         a, cg);
 }
 
 template <typename T, int SRC, int PPT>
@@ -455,6 +640,14 @@ static void fwd_dispatch_rs(const GridPlan& g, const PlaneArgs& a, CGState* cg, 
 template <typename T, int SRC>
 static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const int ppt = plane_ppt(g);
+  if constexpr (SRC == PF_DIV) {
+    // compiled to 17 points per thread (factorised_fits)
+    if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
+    else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
+    else if (plane_radix_set(g) == (RS_8 | RS_2)) fwd_launch<T, SRC, 17, RS_8 | RS_2>(g, a, cg, st);
+    else fwd_launch<T, SRC, 17, RS_ALL>(g, a, cg, st);
+    return;
+  }
   if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
   else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
   else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) fwd_launch<T, SRC, 17, RS_8 | RS_2>(g, a, cg, st);
@@ -466,10 +659,12 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState*
   if (fp32) {
     if (a.src == PF_T) fwd_dispatch<float, PF_T>(g, a, cg, st);
     else if (a.src == PF_F64) fwd_dispatch<float, PF_F64>(g, a, cg, st);
+    else if (a.src == PF_DIV) fwd_dispatch<float, PF_DIV>(g, a, cg, st);
     else fwd_dispatch<float, PF_FPI>(g, a, cg, st);
   } else {
     if (a.src == PF_T) fwd_dispatch<double, PF_T>(g, a, cg, st);
     else if (a.src == PF_F64) fwd_dispatch<double, PF_F64>(g, a, cg, st);
+    else if (a.src == PF_DIV) fwd_dispatch<double, PF_DIV>(g, a, cg, st);
     else fwd_dispatch<double, PF_FPI>(g, a, cg, st);
   }
 }
@@ -477,7 +672,8 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState*
 template <typename T, int MODE, int PPT, int RS>
 static void inv_launch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_inv<T, MODE, PPT, RS>, dim3(9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g, a);
+  launch(k_plane_inv<T, MODE, PPT, RS>, dim3(MODE == PI_OUT_T ? 3 : 9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st,
+         g, a);
 }
 
 template <typename T, int MODE, int PPT>
@@ -493,6 +689,13 @@ static void inv_dispatch_rs(const GridPlan& g, const PlaneInvArgs& a, hipStream_
 template <typename T, int MODE>
 static void inv_dispatch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const int ppt = plane_ppt(g);
+  if constexpr (MODE == PI_OUT_T) {
+    if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
+    else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
+    else if (plane_radix_set(g) == (RS_8 | RS_2)) inv_launch<T, MODE, 17, RS_8 | RS_2>(g, a, st);
+    else inv_launch<T, MODE, 17, RS_ALL>(g, a, st);
+    return;
+  }
   if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
   else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
   else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) inv_launch<T, MODE, 17, RS_8 | RS_2>(g, a, st);
@@ -504,15 +707,36 @@ void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipSt
   if (fp32) {
     if (a.mode == PI_CG) inv_dispatch<float, PI_CG>(g, a, st);
     else if (a.mode == PI_RESID) inv_dispatch<float, PI_RESID>(g, a, st);
+    else if (a.mode == PI_OUT_T) inv_dispatch<float, PI_OUT_T>(g, a, st);
     else inv_dispatch<float, PI_OUT64>(g, a, st);
   } else {
     if (a.mode == PI_CG) inv_dispatch<double, PI_CG>(g, a, st);
     else if (a.mode == PI_RESID) inv_dispatch<double, PI_RESID>(g, a, st);
+    else if (a.mode == PI_OUT_T) inv_dispatch<double, PI_OUT_T>(g, a, st);
     else inv_dispatch<double, PI_OUT64>(g, a, st);
   }
 }
 
 int plane_blocks(const GridPlan& g) { return 9 * g.nz; }
+
+bool factorised_fits(const GridPlan& g) { return g.freq == FREQ_ROTATED && plane_ppt(g) <= 17; }
+
+// Columns of 256 threads over the plane, z chunks of lz planes: the smallest lz that keeps
+// the grid (and the p.q partials) at 1024 blocks.
+int grad_lz(const GridPlan& g) {
+  const int bx = (g.nx * g.ny + 255) / 256;
+  int lz = 1;
+  while ((int64_t)bx * ((g.nz + lz - 1) / lz) > 1024) ++lz;
+  return lz;
+}
+
+int grad_blocks(const GridPlan& g, int lz) { return ((g.nx * g.ny + 255) / 256) * ((g.nz + lz - 1) / lz); }
+
+void launch_cg_grad(const GridPlan& g, bool fp32, const GradArgs& a, hipStream_t st) {
+  const dim3 grid((g.nx * g.ny + 255) / 256, (g.nz + a.lz - 1) / a.lz);
+  if (fp32) launch(k_cg_grad<float>, grid, dim3(256), 0u, st, g, a);
+  else launch(k_cg_grad<double>, grid, dim3(256), 0u, st, g, a);
+}
 
 int prep_blocks(const GridPlan& g) {
   const int64_t nb = (g.nvox + 255) / 256;

@@ -285,7 +285,7 @@ struct Plan {
 };
 
 // Sizes, radix plans, tile widths and divisors of a grid (no tables, nothing allocated).
-static void plan_geometry(GridPlan& g, const int n[3], int tz_choice = 0) {
+static void plan_geometry(GridPlan& g, const int n[3], int tz_choice = 0, int tz3_choice = 0) {
   for (int d = 0; d < 3; ++d)
     if (n[d] < 1 || n[d] > 256) throw Error(RVE_EINVAL, "grid sizes must lie in 1..256");
   g.nx = n[0];
@@ -306,12 +306,20 @@ static void plan_geometry(GridPlan& g, const int n[3], int tz_choice = 0) {
   // kx columns per z-pass block: nz * tz <= 256, i.e. at most 9 points per thread of a
   // 256-thread block (the z-pass transform is compiled for that bound)
   g.tz = std::max(1, std::min(g.nxh, 256 / g.nz));
+  // the three-component z pass: the same columns per block by default (a third of the
+  // work per block), up to three times as many (the same points per thread)
+  g.tz3 = g.tz;
   if (tz_choice > 0) g.tz = std::min(g.tz, tz_choice);
-  if (settings().tz_cap > 0) g.tz = std::min(g.tz, settings().tz_cap);
+  if (tz3_choice > 0) g.tz3 = std::max(1, std::min(std::min(g.nxh, 768 / g.nz), tz3_choice));
+  if (settings().tz_cap > 0) {
+    g.tz = std::min(g.tz, settings().tz_cap);
+    g.tz3 = std::min(g.tz3, settings().tz_cap);
+  }
   g.fnx = make_fastdiv(g.nx);
   g.fnxh = make_fastdiv(g.nxh);
   g.fnz = make_fastdiv(g.nz);
   g.ftz = make_fastdiv(g.tz);
+  g.ftz3 = make_fastdiv(g.tz3);
   g.freq = FREQ_ROTATED;
 }
 
@@ -320,20 +328,24 @@ struct TuneKey {
   int n0, n1, n2, fp32;
   bool operator==(const TuneKey& o) const { return n0 == o.n0 && n1 == o.n1 && n2 == o.n2 && fp32 == o.fp32; }
 };
+struct TunedTiles {
+  int tz = 0, tz3 = 0;  // 0: not tuned
+};
 static std::mutex g_tune_mu;
-static std::vector<std::pair<TuneKey, int>> g_tuned_tz;
+static std::vector<std::pair<TuneKey, TunedTiles>> g_tuned_tz;
 
-static int tuned_tz(const int n[3], bool fp32) {
+static TunedTiles tuned_tz(const int n[3], bool fp32) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   const TuneKey k{n[0], n[1], n[2], fp32 ? 1 : 0};
   for (const auto& e : g_tuned_tz)
     if (e.first == k) return e.second;
-  return 0;
+  return TunedTiles{};
 }
 
 static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false, int freq = FREQ_ROTATED) {
   GridPlan& g = P.g;
-  plan_geometry(g, n, autotune ? tuned_tz(n, fp32) : 0);
+  const TunedTiles tt = autotune ? tuned_tz(n, fp32) : TunedTiles{};
+  plan_geometry(g, n, tt.tz, tt.tz3);
   g.freq = freq;
   // table of roots: tw[k] = exp(-2 pi i k / n); E[q] = exp(+2 pi i q / n) exact at quarter turns
   for (int d = 0; d < 3; ++d) {
@@ -383,7 +395,9 @@ struct Work {
   bool ready = false;
   Plan plan;
   DevBuf K, xa, xb, xbest, r, p, q, y, spec;
+  DevBuf w3;           // factorised projection: the three components w_i (T)
   bool plane = false;  // x/y transforms of one component plane in LDS (when it fits)
+  bool g3 = false;     // CG iterations take the factorised projection
   bool k16 = false;    // FP32 work set with the plane path: tangent copy as scaled FP16 pairs
   bool k_ready = false;  // K holds the tangent of the last constitutive evaluation with tangent
   // captured CG chunks (one HIP graph each), by [tangent transposed][CG unknown xa or xb]
@@ -489,6 +503,22 @@ static int64_t bytes_plane_inv_cg(const GridPlan& g, bool fp32) {
   const int t = fp32 ? 4 : 8;
   return 9 * 2 * t * g.nspec + 45 * t * g.nvox;  // spectrum, r read; p, q read and written
 }
+// factorised projection: y read and three spectra written; three spectra read and written;
+// three spectra read and w written; w, r read, p, q read and written (first iteration: w, r
+// read, p, q written)
+static int64_t bytes_plane_div(const GridPlan& g, bool fp32) {
+  const int t = fp32 ? 4 : 8;
+  return 9 * t * g.nvox + 3 * 2 * t * g.nspec;
+}
+static int64_t bytes_mid3(const GridPlan& g, bool fp32) { return 2 * 3 * 2 * (fp32 ? 4 : 8) * g.nspec; }
+static int64_t bytes_plane_inv3(const GridPlan& g, bool fp32) {
+  const int t = fp32 ? 4 : 8;
+  return 3 * 2 * t * g.nspec + 3 * t * g.nvox;
+}
+static int64_t bytes_cg_grad(const GridPlan& g, bool fp32, bool first) {
+  const int t = fp32 ? 4 : 8;
+  return (first ? 30 : 48) * t * g.nvox;
+}
 static int64_t bytes_plane_fwd_f64(const GridPlan& g, bool fp32) {
   return 9 * 8 * g.nvox + 9 * 2 * (fp32 ? 4 : 8) * g.nspec;  // FP64 field read, spectrum written
 }
@@ -527,6 +557,7 @@ struct RVE {
   bool proj_ready = false;
   bool autotune = false;          // plans take the autotuned z-pass tile width
   int freq = FREQ_ROTATED;        // frequency scheme of the projection and the curl
+  bool factorised = true;         // factorised projection in the CG iterations where it applies
   DevBuf d_C;                     // per-grain C11, C12, C44 (empty: the material's)
   LaunchTimer* tm() { return timer.mask ? &timer : nullptr; }
   ~RVE() {
@@ -549,6 +580,7 @@ struct Ctx {
   int workers = 8;               // host threads driving RVEs concurrently
   bool use_graph = false;        // CG chunks as captured HIP graphs
   int freq = FREQ_ROTATED;       // frequency scheme of the projection and the curl
+  bool factorised = true;        // factorised projection in the CG iterations where it applies
   int max_cutbacks = 0;          // halvings of the time step of a failed increment
   int max_continuation = 16;     // load-continuation stages of a failed FP64 attempt
   bool autotune = false;         // autotuned z-pass tile widths
@@ -584,6 +616,8 @@ static Work& work(RVE& R, bool fp32) {
     w.ready = true;
   }
   w.plane = plane_enabled() && plane_fits(w.plan.g, fp32);
+  w.g3 = R.factorised && w.plane && factorised_fits(w.plan.g);
+  if (w.g3 && !w.w3.p) w.w3.alloc(tsize(fp32) * 3 * (size_t)R.nvox);
   // (K is allocated at the FP32 size, which holds the FP16 pairs too)
   w.k16 = fp32 && w.plane && tangent16_enabled();
   return w;
@@ -610,6 +644,7 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   R.mat = make_material(d.material);
   R.rho0 = initial_rho0(d.material, R.mat);
   R.freq = C.freq;
+  R.factorised = C.factorised;
   if (d.grain_elastic) {
     for (int gi = 0; gi < d.n_grains; ++gi) {
       const double* c = d.grain_elastic + 3 * gi;
@@ -939,6 +974,39 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pi.q = w.q.p;
   pi.cg = cg;
   pi.partial = part + 2048;
+  // factorised projection (w.g3): partials of the stages in disjoint ranges of part:
+  // [0, 1024) r.r of the prep, [2048, 3072) p.q of the gradient pass, [3584, 3593) the
+  // zero-frequency term, [4096, 4096 + 9 nz) plane sums of y
+  PlaneArgs pd{PF_DIV, w.y.p, w.spec.p};
+  pd.rr_partial = part;
+  pd.n_rr = prep_blocks(g);
+  pd.plane_sums = part + 4096;
+  MidArgs m3;
+  std::memset(&m3, 0, sizeof(m3));
+  m3.op = MID_GREEN3;
+  m3.spec = w.spec.p;
+  m3.inv_n = 1.0 / (double)g.nvox;
+  m3.cg = cg;
+  PlaneInvArgs pi3;
+  std::memset(&pi3, 0, sizeof(pi3));
+  pi3.mode = PI_OUT_T;
+  pi3.spec = w.spec.p;
+  pi3.cg = cg;
+  pi3.out = w.w3.p;
+  pi3.plane_sums = part + 4096;
+  pi3.dc = part + 3584;
+  for (int c = 0; c < 9; ++c) pi3.mask_keep[c] = mask_keep[c];
+  pi3.inv_n = 1.0 / (double)g.nvox;
+  GradArgs ga;
+  std::memset(&ga, 0, sizeof(ga));
+  ga.w = w.w3.p;
+  ga.dc = part + 3584;
+  ga.r = w.r.p;
+  ga.p = w.p.p;
+  ga.q = w.q.p;
+  ga.cg = cg;
+  ga.partial = part + 2048;
+  ga.lz = grad_lz(g);
   const int chunk = 4;
   int issued = 0;  // CG iterations launched so far
   auto issue_chunk = [&]() {
@@ -950,6 +1018,27 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
       {
         TimedLaunch t(R.tm(), KF_CG_PREP, bytes_cg_prep(g, w.fp32, w.k16, issued == 0), R.stream);
         launch_cg_prep(g, w.fp32, w.k16, transpose, pr, R.stream);
+      }
+      if (w.g3) {
+        pd.it = issued;
+        {
+          TimedLaunch t(R.tm(), KF_PLANE_DIV, bytes_plane_div(g, w.fp32), R.stream);
+          launch_plane_fwd(g, w.fp32, pd, cg, R.stream);
+        }
+        {
+          TimedLaunch t(R.tm(), KF_MID3, bytes_mid3(g, w.fp32), R.stream);
+          launch_mid(g, w.fp32, m3, R.stream);
+        }
+        {
+          TimedLaunch t(R.tm(), KF_PLANE_W, bytes_plane_inv3(g, w.fp32), R.stream);
+          launch_plane_inv(g, w.fp32, pi3, R.stream);
+        }
+        {
+          TimedLaunch t(R.tm(), KF_CG_GRAD, bytes_cg_grad(g, w.fp32, issued == 0), R.stream);
+          launch_cg_grad(g, w.fp32, ga, R.stream);
+        }
+        launch_cg_alpha(cg, part + 2048, grad_blocks(g, ga.lz), R.stream);
+        continue;
       }
       {
         TimedLaunch t(R.tm(), KF_PLANE_FWD, bytes_plane_fwd_cg(g, w.fp32), R.stream);
@@ -1506,37 +1595,47 @@ static void noalloc_plan(GridPlan& g, const int n[3], bool fp32, unsigned char* 
 // The autotuner: for a grid size and spectral precision, time the z pass (z transforms and
 // the projection of eq. 17) at each candidate tile width (kx columns per block: the widest
 // that the 256-thread block holds, then halvings down to 1) and keep the fastest for the
-// process.  The tile width changes the work split, not the arithmetic of any line or
-// frequency, so the choice does not change results.  Runs once per (grid, precision), on
-// the creating thread, before any worker exists.
+// process; the same for the three-component z pass of the factorised projection.  The tile
+// width changes the work split, not the arithmetic of any line or frequency, so the choice
+// does not change results.  Runs once per (grid, precision), on the creating thread, before
+// any worker exists.
 static void autotune_grid(const int32_t n_in[3], bool fp32) {
   const int n[3] = {n_in[0], n_in[1], n_in[2]};
-  if (tuned_tz(n, fp32) > 0) return;
+  if (tuned_tz(n, fp32).tz > 0) return;
   Plan P;
   build_plan(P, n, fp32, false);
   const GridPlan base = P.g;
-  std::vector<int> cand;
-  for (int t = base.tz; t >= 1; t /= 2) cand.push_back(t);
-  int best = base.tz;
-  if (cand.size() > 1) {
-    DevBuf spec;
-    spec.alloc(tsize(fp32) * 2 * 9 * (size_t)base.nspec);
-    HIPCHECK(hipMemset(spec.p, 0, spec.bytes));
-    hipStream_t st = nullptr;
-    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHECK(hipEventCreate(&e0));
-    HIPCHECK(hipEventCreate(&e1));
-    MidArgs m;
-    std::memset(&m, 0, sizeof(m));
-    m.op = MID_GREEN;
-    m.spec = spec.p;
-    m.inv_n = 1.0 / (double)base.nvox;
+  TunedTiles best;
+  best.tz = base.tz;
+  best.tz3 = base.tz3;
+  DevBuf spec;
+  spec.alloc(tsize(fp32) * 2 * 9 * (size_t)base.nspec);
+  HIPCHECK(hipMemset(spec.p, 0, spec.bytes));
+  hipStream_t st = nullptr;
+  HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  MidArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.spec = spec.p;
+  m.inv_n = 1.0 / (double)base.nvox;
+  // fastest of the candidate widths (first = widest) for one operator
+  auto tune = [&](int op, int widest) {
+    std::vector<int> cand;
+    for (int t = widest; t >= 1; t /= 2) cand.push_back(t);
+    m.op = op;
+    int pick = cand.front();
     float best_ms = 1e30f;
     for (int t : cand) {
       GridPlan g = base;
-      g.tz = t;
-      g.ftz = make_fastdiv(t);
+      if (op == MID_GREEN3) {
+        g.tz3 = t;
+        g.ftz3 = make_fastdiv(t);
+      } else {
+        g.tz = t;
+        g.ftz = make_fastdiv(t);
+      }
       launch_mid(g, fp32, m, st);  // warm-up
       HIPCHECK(hipEventRecord(e0, st));
       for (int r = 0; r < 5; ++r) launch_mid(g, fp32, m, st);
@@ -1545,14 +1644,18 @@ static void autotune_grid(const int32_t n_in[3], bool fp32) {
       check_launch("autotune");
       float ms = 0.f;
       HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-      if (trace_on()) std::fprintf(stderr, "[rve] autotune %dx%dx%d %s: tz %d %.2f us\n", n[0], n[1], n[2],
-                                   fp32 ? "fp32" : "fp64", t, 1e3f * ms / 5.f);
-      if (ms < best_ms) best_ms = ms, best = t;
+      if (trace_on())
+        std::fprintf(stderr, "[rve] autotune %dx%dx%d %s %s: tz %d %.2f us\n", n[0], n[1], n[2], fp32 ? "fp32" : "fp64",
+                     op == MID_GREEN3 ? "3-comp" : "9-comp", t, 1e3f * ms / 5.f);
+      if (ms < best_ms) best_ms = ms, pick = t;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamDestroy(st);
-  }
+    return pick;
+  };
+  best.tz = tune(MID_GREEN, base.tz);
+  if (factorised_fits(base)) best.tz3 = tune(MID_GREEN3, std::max(1, std::min(base.nxh, 768 / base.nz)));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tuned_tz.push_back({TuneKey{n[0], n[1], n[2], fp32 ? 1 : 0}, best});
 }
@@ -1587,6 +1690,8 @@ int32_t rve_create(const rve_desc* descs, int32_t n_rve, const rve_options* opt,
     C->max_cutbacks = o.max_cutbacks;
     if (o.frequencies != FREQ_ROTATED && o.frequencies != FREQ_STANDARD) throw Error(RVE_EINVAL, "unknown frequency scheme");
     C->freq = o.frequencies;
+    if (o.projection != 0 && o.projection != 1) throw Error(RVE_EINVAL, "unknown projection form");
+    C->factorised = o.projection == 0;
     C->max_continuation = o.max_continuation > 0 ? o.max_continuation : 16;
     C->autotune = o.autotune != 0;
     if (C->autotune)

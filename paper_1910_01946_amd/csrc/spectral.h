@@ -19,8 +19,9 @@ struct GridPlan {
   const void* Ez;
   int ly;            // rows per block in the x passes (even)
   int ty;            // kx columns per block in the y passes
-  int tz;            // kx columns per block in the z pass
-  FastDiv fnx, fnxh, fnz, ftz;  // divisions by nx, nxh, nz, tz
+  int tz;            // kx columns per block in the z pass (nine components)
+  int tz3;           // kx columns per block in the z pass of the factorised projection (three)
+  FastDiv fnx, fnxh, fnz, ftz, ftz3;  // divisions by nx, nxh, nz, tz, tz3
   int freq;          // FREQ_ROTATED (eq. A.4) or FREQ_STANDARD (continuous frequencies)
 };
 
@@ -67,7 +68,11 @@ constexpr int kCgStall = 500;
 
 enum XFwdMode { XF_FIELD64 = 0, XF_CG = 1, XF_FP_MINUS_I = 2 };
 enum XInvMode { XI_RESID = 0, XI_CG = 1, XI_NYE = 2, XI_OUT64 = 3 };
-enum MidOp { MID_GREEN = 0, MID_CURL = 1 };
+// MID_GREEN: the projection of eq. 17 on nine components; MID_CURL: the curl of eq. 12;
+// MID_GREEN3: the middle factor of the factorised projection (see PF_DIV) on three
+// components, w_i = v_i / |k|^2, with the zero frequency and the modes where k vanishes set
+// to zero.
+enum MidOp { MID_GREEN = 0, MID_CURL = 1, MID_GREEN3 = 2 };
 
 struct XFwdArgs {
   int mode;
@@ -163,8 +168,23 @@ void launch_widen(const float* in, double* out, int64_t n, hipStream_t st);
 void launch_negate(const double* in, double* out, int64_t n, hipStream_t st);
 
 // ---- plane path (x and y transforms of one component plane in LDS) ----------------
-enum PlaneSrc { PF_T = 0, PF_F64 = 1, PF_FPI = 2 };
-enum PlaneMode { PI_CG = 0, PI_RESID = 1, PI_OUT64 = 2 };
+//
+// The factorised projection.  With the rotated scheme every component of the modified
+// frequency (eq. A.4) is, up to the common factor -i, the symbol d_j of a real stencil on the
+// 2 x 2 x 2 voxel cube: a forward difference along axis j averaged over the other two axes,
+//   D_j = 1/4 (S_j - 1) prod_{m != j} (1 + S_m),   S_m u(x) = u(x + e_m),
+// and conj(d_j) is the symbol of its adjoint D_j^H (shifts by -e_m).  The projection of
+// eq. 17 away from the zero frequency, (G:A)_ij = k_j sum_l A_il conj(k_l) / |k|^2, is then
+//   G:A = D_j w_i,   w_i = (D^H D)^-1 v_i,   v_i = sum_l D_l^H A_il,   D^H D = |d|^2 = |k|^2,
+// so the transforms carry the three components v_i instead of nine:
+//   k_plane_fwd<PF_DIV>  v_i = sum_l D_l^H y_il on the fly, x and y transforms of v_i;
+//   k_mid<MID_GREEN3>    z transforms, times 1 / (nvox |k|^2), inverse z transforms;
+//   k_plane_inv<PI_OUT_T> inverse y and x transforms, w_i stored;
+//   k_cg_grad            q_ij = D_j w_i + the zero-frequency term, then the CG epilogue.
+// The zero frequency keeps the nine-component rule: its output is mask_keep * <y>, from
+// plane sums that the PF_DIV pass writes and the PI_OUT_T pass reduces.
+enum PlaneSrc { PF_T = 0, PF_F64 = 1, PF_FPI = 2, PF_DIV = 3 };
+enum PlaneMode { PI_CG = 0, PI_RESID = 1, PI_OUT64 = 2, PI_OUT_T = 3 };
 
 struct PlaneArgs {
   int src;                     // PF_T: field of type T; PF_F64: FP64 field; PF_FPI: FP64 Fp - I
@@ -175,6 +195,7 @@ struct PlaneArgs {
   const double* rr_partial;
   int n_rr;
   int it;                      // iteration index within the solve (0 = first)
+  double* plane_sums;          // PF_DIV: sums of y_il over plane z at [(3 i + l) nz + z]
 };
 
 struct PlaneInvArgs {
@@ -187,6 +208,28 @@ struct PlaneInvArgs {
   double* out64;               // PI_OUT64
   CGState* cg;
   double* partial;             // per-block (9 x nz) r.r (PI_RESID) or p.q (PI_CG)
+  // PI_OUT_T: the real planes of the three components, stored as T (3 x nvox); blocks of
+  // plane 0 also reduce the plane sums of PF_DIV to the zero-frequency term
+  // dc[c] = mask_keep[c] sum_z plane_sums[c nz + z] / nvox
+  void* out;
+  const double* plane_sums;
+  double* dc;
+  double mask_keep[9];
+  double inv_n;
+};
+
+// q = D w + dc, then the CG epilogue of k_plane_inv<PI_CG>: q = q + beta q_prev,
+// p = r + beta p, per-block p.q.  Each thread walks lz consecutive z planes of one (x, y)
+// column and carries the corner values of the upper plane to the next step.
+struct GradArgs {
+  const void* w;               // 3 x nvox (T)
+  const double* dc;            // 9 values
+  const void* r;
+  void* p;
+  void* q;
+  CGState* cg;
+  double* partial;             // per-block p.q
+  int lz;                      // z planes per thread
 };
 
 struct PrepArgs {
@@ -211,6 +254,13 @@ hipError_t set_spectral_lds_limits(int bytes);
 hipError_t set_plane_lds_limits(int bytes);
 int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
+// The factorised projection runs with the rotated scheme only, on grids that take the plane
+// path and whose planes have at most 17 points per thread of the plane kernels (planes to
+// about 128 x 128); the caller checks plane_fits for its precision.
+bool factorised_fits(const GridPlan& g);
+int grad_blocks(const GridPlan& g, int lz);
+int grad_lz(const GridPlan& g);
+void launch_cg_grad(const GridPlan& g, bool fp32, const GradArgs& a, hipStream_t st);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
 // k16: the tangent copy is FP16 pairs scaled by 1/k_scale (grouped layout of

@@ -176,7 +176,10 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   if (a.cg && a.cg->done) return;
-  const int ny = g.ny, nz = g.nz, nxh = g.nxh, tz = g.tz, SZ = padded_len(nz);
+  // components carried: nine, or the three of the factorised projection
+  constexpr int NC = OP == MID_GREEN3 ? 3 : 9;
+  const int ny = g.ny, nz = g.nz, nxh = g.nxh, tz = NC == 3 ? g.tz3 : g.tz, SZ = padded_len(nz);
+  const FastDiv ftz = NC == 3 ? g.ftz3 : g.ftz;
   // XCD-aware order: consecutive hardware block ids are dealt to the 8 XCDs in turn; each
   // XCD takes a contiguous range of (ky, kx tile) so that the cache lines shared by
   // neighbouring tiles and rows are fetched and written back through a single L2.
@@ -189,9 +192,9 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.spec);
   // one contiguous padded z line per (component, kx column): line c * tz + j
-  cplx<T>* twz = buf + 9 * tz * SZ;
+  cplx<T>* twz = buf + NC * tz * SZ;
   load_twiddles(twz, g.twz, nz);
-  const int nload = 9 * nz * tz;
+  const int nload = NC * nz * tz;
   // 8 independent loads in flight per thread before the LDS writes
   for (int b0 = tid; b0 < nload; b0 += 8 * nthr) {
     cplx<T> val[8];
@@ -200,7 +203,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
       const int idx = b0 + u * nthr;
       val[u] = cmk((T)0, (T)0);
       if (idx < nload) {
-        const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+        const int t = fdiv(idx, ftz), j = idx - t * tz;
         const int c = fdiv(t, g.fnz), zz = t - c * nz;
         if (kx0 + j < nxh) val[u] = spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j];
       }
@@ -209,20 +212,20 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     for (int u = 0; u < 8; ++u) {
       const int idx = b0 + u * nthr;
       if (idx < nload) {
-        const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+        const int t = fdiv(idx, ftz), j = idx - t * tz;
         const int c = fdiv(t, g.fnz), zz = t - c * nz;
         buf[(c * tz + j) * SZ + padded(zz)] = val[u];
       }
     }
   }
   __syncthreads();
-  LineLayout L{9 * tz, 1, SZ, 0, 0};
+  LineLayout L{NC * tz, 1, SZ, 0, 0};
   fft_lines<T, 9, RS>(buf, L, g.az, twz, (T)-1);
   const cplx<double>* Ex = reinterpret_cast<const cplx<double>*>(g.Ex);
   const cplx<double>* Ey = reinterpret_cast<const cplx<double>*>(g.Ey);
   const cplx<double>* Ez = reinterpret_cast<const cplx<double>*>(g.Ez);
   for (int idx = tid; idx < nz * tz; idx += nthr) {
-    const int kz = fdiv(idx, g.ftz), j = idx - kz * tz, kx = kx0 + j;
+    const int kz = fdiv(idx, ftz), j = idx - kz * tz, kx = kx0 + j;
     if (kx >= nxh) continue;
     // modified frequency vector of the rotated scheme (eq. A.4):
     // k_i = 1/4 (-i)(E_i - 1) prod_{j != i} (1 + E_j)
@@ -245,6 +248,16 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
     const bool dc = kx == 0 && ky == 0 && kz == 0;
     const double k2 = kv[0].x * kv[0].x + kv[0].y * kv[0].y + kv[1].x * kv[1].x + kv[1].y * kv[1].y +
                       kv[2].x * kv[2].x + kv[2].y * kv[2].y;
+    if constexpr (OP == MID_GREEN3) {
+      // w_i = v_i / (nvox |k|^2); v has no zero-frequency content (a sum of differences)
+      const double s = (dc || k2 == 0.0) ? 0.0 : a.inv_n / k2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        cplx<T>& e = buf[(i * tz + j) * SZ + padded(kz)];
+        e = cmk((T)(s * (double)e.x), (T)(s * (double)e.y));
+      }
+      continue;
+    }
     cplx<double> ik[3];
     if (OP != MID_GREEN) {
       // alpha_ij = eps_jml (i k_m / h) Fp_il
@@ -292,7 +305,7 @@ __global__ void k_mid(GridPlan g, MidArgs a) {
   __syncthreads();
   fft_lines<T, 9, RS>(buf, L, g.az, twz, (T)1);
   for (int idx = tid; idx < nload; idx += nthr) {
-    const int t = fdiv(idx, g.ftz), j = idx - t * tz;
+    const int t = fdiv(idx, ftz), j = idx - t * tz;
     const int c = fdiv(t, g.fnz), zz = t - c * nz;
     if (kx0 + j < nxh) spec[(((int64_t)c * nz + zz) * ny + ky) * nxh + kx0 + j] = buf[(c * tz + j) * SZ + padded(zz)];
   }
@@ -519,6 +532,7 @@ static hipError_t mid_limits(int bytes) {
   hipError_t e = hipSuccess, f;
   if ((f = lds_limit(k_mid<T, MID_GREEN, RS>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_mid<T, MID_CURL, RS>, bytes)) != hipSuccess) e = f;
+  if ((f = lds_limit(k_mid<T, MID_GREEN3, RS>, bytes)) != hipSuccess) e = f;
   return e;
 }
 
@@ -581,15 +595,16 @@ void launch_yfft(const GridPlan& g, bool fp32, void* spec, int sign, const CGSta
   }
 }
 
-int mid_blocks(const GridPlan& g) {
-  const int nblk = ((g.nxh + g.tz - 1) / g.tz) * g.ny;
+static int mid_blocks(const GridPlan& g, int tz) {
+  const int nblk = ((g.nxh + tz - 1) / tz) * g.ny;
   return 8 * ((nblk + 7) / 8);
 }
 
 template <typename T, int OP, int RS>
 static void mid_launch(const GridPlan& g, const MidArgs& a, hipStream_t st) {
-  const size_t sh = ((size_t)9 * g.tz * padded_len(g.nz) + g.nz) * sizeof(cplx<T>);
-  launch(k_mid<T, OP, RS>, dim3(mid_blocks(g)), dim3(256), (uint32_t)sh, st, g, a);
+  const int nc = OP == MID_GREEN3 ? 3 : 9, tz = OP == MID_GREEN3 ? g.tz3 : g.tz;
+  const size_t sh = ((size_t)nc * tz * padded_len(g.nz) + g.nz) * sizeof(cplx<T>);
+  launch(k_mid<T, OP, RS>, dim3(mid_blocks(g, tz)), dim3(256), (uint32_t)sh, st, g, a);
 }
 
 // radix set of the z transform
@@ -606,9 +621,11 @@ static void mid_dispatch(const GridPlan& g, const MidArgs& a, hipStream_t st) {
 void launch_mid(const GridPlan& g, bool fp32, const MidArgs& a, hipStream_t st) {
   if (fp32) {
     if (a.op == MID_GREEN) mid_dispatch<float, MID_GREEN>(g, a, st);
+    else if (a.op == MID_GREEN3) mid_dispatch<float, MID_GREEN3>(g, a, st);
     else mid_dispatch<float, MID_CURL>(g, a, st);
   } else {
     if (a.op == MID_GREEN) mid_dispatch<double, MID_GREEN>(g, a, st);
+    else if (a.op == MID_GREEN3) mid_dispatch<double, MID_GREEN3>(g, a, st);
     else mid_dispatch<double, MID_CURL>(g, a, st);
   }
 }

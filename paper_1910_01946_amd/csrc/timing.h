@@ -16,7 +16,11 @@ enum KernelFamily {
   KF_PLANE_FWD = 4,      // x and y forward transforms of one component plane
   KF_MID = 5,            // z transforms and the Green operator
   KF_PLANE_INV = 6,      // y and x inverse transforms and the CG epilogue
-  KF_COUNT = 7
+  KF_CG_GRAD = 7,        // gradient stencil of the factorised projection and the CG epilogue
+  KF_PLANE_DIV = 8,      // divergence stencil and x and y forward transforms (factorised)
+  KF_MID3 = 9,           // z transforms and 1 / |k|^2 on three components (factorised)
+  KF_PLANE_W = 10,       // y and x inverse transforms of three components (factorised)
+  KF_COUNT = 11
 };
 
 // Receives a mark before and after every launch of a family (the launch itself goes

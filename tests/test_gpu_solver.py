@@ -142,6 +142,59 @@ def test_ragged_grid_fp64_matches_oracle(lib):
     _check_gnd_fields(h, o, rve)
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 9, 10), (6, 5, 4)])
+def test_factorised_projection_equals_the_nine_component_form(lib, shape):
+    """The CG operator as divergence stencil, three transforms, 1/|k|^2 and gradient stencil
+    (projection 0) against the nine-component projection of eq. 17 (projection 1), FP64, two
+    whole increments at tight tolerances, on even planes and on planes with an odd row count:
+    <P> within 1e-11 and the F field within 1e-11 (the forms differ by rounding only), and the
+    timed families show that each form ran."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    rve = synth.voronoi_rve(501, shape, 5, 2e-6, mat)
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    res = {}
+    for form in (0, 1):
+        h = lib.Homogenizer([rve], precision=lib.RVE_FP64, newton_tol=1e-13, cg_tol=1e-12, max_cg=4000,
+                            projection=form)
+        h.timing_start(["cg_grad"])
+        Ps = []
+        for k in (1, 2):
+            print(f"form {form} shape {shape} increment {k}", flush=True)
+            st = h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)[0]
+            Ps.append(h.macro()[0])
+        n_grad = h.timing_read("cg_grad")[0]
+        assert (n_grad > 0) == (form == 0), n_grad
+        res[form] = (np.array(Ps), from_abi(h.field("F")), st["cg_iters"])
+        h.close()
+    dP = np.abs(res[0][0] - res[1][0]).max() / np.abs(res[1][0]).max()
+    dF = rel_norm(res[0][1], res[1][1])
+    print("  <P> difference", dP, "F difference", dF, "cg", res[0][2], res[1][2], flush=True)
+    assert dP <= 1e-11
+    assert dF <= 1e-11
+
+
+def test_factorised_projection_mixed_form_matches_fp64(lib):
+    """The mixed form with the factorised CG operator on the 16^3 workload at the benchmark
+    tolerances: no FP64 fallback and <P>_11 within 1e-4 of the FP64 nine-component form over
+    10 increments."""
+    rves, path = synth.workload("cu16")
+    curves = {}
+    for prec, form in ((lib.RVE_MIXED, 0), (lib.RVE_FP64, 1)):
+        h = lib.Homogenizer(rves, precision=prec, newton_tol=1e-6, cg_tol=1e-3, max_cg=3000, max_newton=150,
+                            projection=form)
+        c = []
+        for k in range(1, 11):
+            st = h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)[0]
+            if prec == lib.RVE_MIXED:
+                assert st["fp64_fallback"] == 0, (k, st)
+            c.append(h.macro()[0][0])
+        h.close()
+        curves[prec] = np.array(c)
+    diff = np.abs(curves[lib.RVE_MIXED] - curves[lib.RVE_FP64]) / np.abs(curves[lib.RVE_FP64]).max()
+    print("largest relative <P>_11 difference", diff.max(), flush=True)
+    assert diff.max() <= 1e-4
+
+
 def test_adjoint_solve_matches_oracle_transposed_cg(lib):
     """rve_adjoint_solve after three increments of the 64-grain SGCP workload at 6^3 (FP64):
     lam from G(K^T : lam) = G(g) against the oracle's conjugate gradients with its own tangent
@@ -310,20 +363,23 @@ def test_kernel_timing_counts_live_launches(lib):
     rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
     h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3)
     h.step(path.F_bar[1], path.mask, path.P_bar[1], path.dt)
-    h.timing_start(["cg_prep", "mid", "slip_fast"])
+    h.timing_start(["cg_prep", "mid", "mid3", "slip_fast"])
     st = h.step(path.F_bar[2], path.mask, path.P_bar[2], path.dt)[0]
     n_prep, ms_prep, b_prep = h.timing_read("cg_prep")
     n_mid, ms_mid, b_mid = h.timing_read("mid")
+    n_mid3, ms_mid3, b_mid3 = h.timing_read("mid3")
     n_fast, _, vox = h.timing_read("slip_fast")
     assert n_fast >= 1 and vox == n_fast * rves[0].n_vox
-    # every CG iteration applies the operator once; residual evaluations add one z pass each
-    assert n_mid == st["cg_iters"] + st["residual_evals"]
+    # every CG iteration applies the operator once, in the factorised form (three components in
+    # the z pass); each residual evaluation takes one nine-component z pass
+    assert n_mid3 == st["cg_iters"] and n_mid == st["residual_evals"]
     assert st["cg_iters"] <= n_prep <= st["cg_iters"] + st["newton_iters"]
     assert ms_mid > 0 and b_mid == n_mid * 2 * 9 * 2 * 4 * 5 * 8 * 8
+    assert ms_mid3 > 0 and b_mid3 == n_mid3 * 2 * 3 * 2 * 4 * 5 * 8 * 8
     assert h.timing_read("plane_fwd")[0] == 0          # not selected
     h.timing_start([])
     with pytest.raises(lib.RVEError):
-        lib.check(lib.lib().rve_timing_start(h.h, 1 << 9))        # unknown family bit
+        lib.check(lib.lib().rve_timing_start(h.h, 1 << 11))       # unknown family bit
 
 
 def test_cu64_mixed_runs_the_whole_path_in_fp32_within_1e4_of_the_fp64_form(lib):
