@@ -95,6 +95,11 @@ def parse():
     ap.add_argument("--replay", type=int, default=2, help="timed increments replayed for the roofline")
     ap.add_argument("--rves", type=int, default=None, help="use only the first R RVEs of the workload")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--profiles-dir", default=None, help="where the summaries go (default: profiles/)")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="write profiles/kernels_* from the kernel trace under DIR (see TRACE_RUNS)")
+    ap.add_argument("--summarize-counters", default=None, metavar="DIR",
+                    help="write profiles/pmc_* from the counter runs under DIR (see COUNTER_RUNS)")
     return ap.parse_args()
 
 
@@ -222,32 +227,45 @@ def timed(h, path, first, K, tag):
     return {"T": time.perf_counter() - t0, "vi": vi, "discarded_vi": disc, "per_increment": per_inc, "P11": P}
 
 
-class ProfilerRegion:
-    """The replay is the region a profiler run with rocprofv3 --selected-regions records:
-    roctxProfilerResume(0) before it and roctxProfilerPause(0) after it (no effect without a
-    profiler; skipped if the ROCm tracer library is absent)."""
+def _load_roctx():
+    """The profiler-control entry points (rocprofiler-sdk's tracer library; the older libroctx64,
+    also bundled with torch, lacks them), loaded before HIP starts so that a profiler in the
+    process registers them; None when absent."""
+    import ctypes
 
-    def __init__(self):
-        import ctypes
-        self.L = None
-        for name in ("libroctx64.so", "/opt/rocm/lib/libroctx64.so"):
-            try:
-                self.L = ctypes.CDLL(name)
-                break
-            except OSError:
-                continue
-        if self.L is not None:
-            self.L.roctxProfilerResume.argtypes = [ctypes.c_uint64]
-            self.L.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+    for name in ("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so.1"):
+        try:
+            L = ctypes.CDLL(name)
+            L.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+            L.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+            return L
+        except (OSError, AttributeError):
+            continue
+    return None
+
+
+_ROCTX = None
+
+
+class ProfilerRegion:
+    """The serialised replay, marked for profilers: roctxProfilerResume(0) before it and
+    roctxProfilerPause(0) after it (for rocprofv3 --selected-regions; no effect without a
+    profiler), and one fill kernel (a torch.full) right before its first launch, after which a
+    trace or counter run of the whole process is summarised."""
 
     def __enter__(self):
-        if self.L is not None:
-            self.L.roctxProfilerResume(0)
+        import torch
+
+        if _ROCTX is not None:
+            _ROCTX.roctxProfilerResume(0)
+        # marker for a trace of the whole process: one fill kernel right before the replay
+        torch.full((1,), 7.0, device="cuda")
+        torch.cuda.synchronize()
         return self
 
     def __exit__(self, *exc):
-        if self.L is not None:
-            self.L.roctxProfilerPause(0)
+        if _ROCTX is not None:
+            _ROCTX.roctxProfilerPause(0)
         return False
 
 
@@ -298,6 +316,23 @@ def roofline(fam, T, workload):
         out.update({"bound": "alu", "achieved": None, "peak": 78.6, "unit": "TFLOP/s", "frac": None,
                     "traffic": None, "launches": n, "avg_launch_us": 1e3 * ms / max(n, 1)})
     out["spectral_kernels"] = per
+    # the constitutive kernels against the FP64 vector peak (flops per launch from counters)
+    cons = []
+    for _, f in CONST_FAMILIES:
+        n, ms, units = fam[f]
+        if n == 0:
+            continue
+        fl = stored_flops(f, workload)
+        ach = fl * n / (ms * 1e-3) / 1e12 if fl else None
+        cons.append({"family": f, "kernel": FAMILY_KERNELS[f][0], "bound": "alu", "launches": n,
+                     "avg_launch_us": 1e3 * ms / n, "flops_per_launch": fl, "achieved": ach,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / FP64_PEAK_TFLOPS if ach else None, "share": round(share[f], 4)})
+    out["constitutive_kernels"] = cons
+    if dom not in SPECTRAL:
+        d = next((c for c in cons if c["family"] == dom), None)
+        if d and d["frac"] is not None:
+            out.update({"achieved": d["achieved"], "frac": d["frac"]})
     return out
 
 
@@ -315,8 +350,233 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
 
 
+# Counter runs behind the committed summaries (from the repository root R on one MI355X; one host
+# worker; only the dispatches after the replay marker are summarised):
+COUNTER_RUNS = """cd /tmp && export TMPDIR=/tmp && export RVE_WORKERS=1
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_f -o c -- python3 $R/bench.py --copy-calibration
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_w -o c -- python3 $R/bench.py --copy-calibration
+rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_f -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline
+rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_w -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline > $R/gpurun_out/pmc_w_bench.json
+rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU SQ_BUSY_CYCLES --kernel-include-regex "FillFunctor|k_slip_fast|k_slip_slow|k_stress_tangent" --output-format csv -d $R/gpurun_out/pmc_valu -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline
+python3 bench.py --summarize-counters gpurun_out --profiles-dir gpurun_out/summaries   (then copied to profiles/)"""
+CONST_FAMILIES = (("k_slip_fast", "slip_fast"), ("k_slip_slow", "slip_slow"), ("k_stress_tangent<", "stress_tangent"))
+FP64_PEAK_TFLOPS = 78.6
+SPECTRAL_REGEX = "FillFunctor|k_cg_prep|k_plane_fwd|k_mid|k_plane_inv|k_cg_grad"
+# template arguments that tell the spectral families apart in the demangled kernel names
+# (PF_F64 = 1, PF_DIV = 3; MID_GREEN = 0, MID_GREEN3 = 2; PI_RESID = 1, PI_OUT_T = 3)
+_NAME_FAMILY = [(r"k_cg_prep<float, 1, 0>", "cg_prep"), (r"k_plane_fwd<float, 3,", "plane_div"),
+                (r"k_plane_fwd<float, 1,", "plane_fwd"), (r"k_mid<float, 2,", "mid3"), (r"k_mid<float, 0,", "mid"),
+                (r"k_plane_inv<float, 3,", "plane_w"), (r"k_plane_inv<float, 1,", "plane_inv"),
+                (r"k_cg_grad<float>", "cg_grad")]
+
+
+def _counter_rows(directory, after_marker=True):
+    """(kernel name, counter, value) of the dispatches in the rocprofv3 CSV files under directory;
+    with after_marker, only those after the last replay marker (the fill kernel that bench.py
+    launches right before its serialised replay)."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                did = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0)
+                rows.append((did, r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    rows.sort(key=lambda t: t[0])
+    if after_marker:
+        marks = [d for d, n, _, _ in rows if "FillFunctor" in n]
+        if not marks:
+            raise SystemExit(f"no replay marker among the dispatches under {directory}")
+        rows = [r for r in rows if r[0] > max(marks)]
+    return [(n, c, v) for _, n, c, v in rows]
+
+
+def summarize_counters(out_dir, workload="sweep32", profiles=None):
+    """Write profiles/pmc_<family>_<workload>_mixed.txt for every spectral family found in the
+    counter runs of COUNTER_RUNS: FETCH_SIZE and WRITE_SIZE per live dispatch (a dispatch that a
+    finished CG solve turned into a no-op reads and writes a few KiB; live ones at least
+    hundreds), each scaled by the same counter's reading of a 2^30-byte copy, against the
+    algorithmic bytes per launch that the bench line of the WRITE_SIZE run reports."""
+    import numpy as np
+
+    def copy_scale(d, counter):
+        vals = [v for k, c, v in _counter_rows(d, after_marker=False) if c == counter and "copy" in k.lower()]
+        if not vals:
+            raise SystemExit(f"no copy dispatches with {counter} under {d}")
+        return (1 << 30) / (1024.0 * float(np.median(vals))), float(np.median(vals))
+
+    if profiles:
+        os.makedirs(profiles, exist_ok=True)
+    s_f, kib_f = copy_scale(os.path.join(out_dir, "pmc_copy_f"), "FETCH_SIZE")
+    s_w, kib_w = copy_scale(os.path.join(out_dir, "pmc_copy_w"), "WRITE_SIZE")
+    line = json.loads(open(os.path.join(out_dir, "pmc_w_bench.json")).read().strip().splitlines()[-1])
+    alg = {p["family"]: p for p in line["roofline"]["spectral_kernels"]}
+    per = {}
+    for counter, d in (("FETCH_SIZE", "pmc_f"), ("WRITE_SIZE", "pmc_w")):
+        for name, c, v in _counter_rows(os.path.join(out_dir, d)):
+            if c != counter:
+                continue
+            fam = next((f for pat, f in _NAME_FAMILY if pat in name), None)
+            if fam:
+                per.setdefault(fam, {}).setdefault(counter, []).append(v)
+    written = []
+    for fam, cs in sorted(per.items()):
+        if fam not in alg or "FETCH_SIZE" not in cs or "WRITE_SIZE" not in cs:
+            continue
+        live = {c: [v for v in vals if v > 64.0] for c, vals in cs.items()}
+        f_mb = 1024.0 * s_f * float(np.mean(live["FETCH_SIZE"])) / 1e6
+        w_mb = 1024.0 * s_w * float(np.mean(live["WRITE_SIZE"])) / 1e6
+        a = alg[fam]
+        traffic = (f_mb + w_mb) * 1e6
+        text = f"""# HBM traffic of {a['instantiation']} on the {workload} workload, mixed form
+# (serialised replay of two increments from the saved state: every RVE of the workload, one at
+# a time, grids of several sizes; per-launch figures are averages over the live launches)
+
+commands (repository root R, one MI355X), one counter per run:
+{COUNTER_RUNS.format(regex=SPECTRAL_REGEX)}
+
+calibration: a device copy of 2^30 bytes, 5 dispatches
+  FETCH_SIZE {kib_f:.1f} KiB per dispatch for 1048576 KiB read     -> scale {s_f:.5f}
+  WRITE_SIZE {kib_w:.1f} KiB per dispatch for 1048576 KiB written  -> scale {s_w:.5f}
+
+{a['instantiation']}: FETCH_SIZE {len(cs['FETCH_SIZE'])} dispatches ({len(live['FETCH_SIZE'])} live), WRITE_SIZE {len(cs['WRITE_SIZE'])} ({len(live['WRITE_SIZE'])} live); the bench's events counted {a['launches']} live launches
+  FETCH_SIZE live mean -> {f_mb:.3f} MB read per launch
+  WRITE_SIZE live mean -> {w_mb:.3f} MB written per launch
+  algorithmic bytes per launch (bench line of the WRITE_SIZE run): {a['algorithmic_bytes_per_launch'] / 1e6:.3f} MB; measured / algorithmic = {traffic / a['algorithmic_bytes_per_launch']:.2f}
+
+traffic_bytes_per_launch = {traffic:.0f}
+source_digest = {source_digest(FAMILY_KERNELS[fam][1])}
+"""
+        path = os.path.join(profiles or os.path.join(ROOT, "profiles"), f"pmc_{fam}_{workload}_mixed.txt")
+        with open(path, "w") as fh:
+            fh.write(text)
+        written.append((fam, traffic / a["algorithmic_bytes_per_launch"]))
+    # FP64 vector work of the constitutive kernels: 64 lanes x (2 FMA + ADD + MUL + TRANS) per
+    # wave instruction (no MFMA on this path), per dispatch
+    vrows = _counter_rows(os.path.join(out_dir, "pmc_valu"))
+    if vrows:
+        by = {}
+        for name, c, v in vrows:
+            fam = next((f for pat, f in CONST_FAMILIES if pat in name), None)
+            if fam:
+                by.setdefault(fam, {}).setdefault(c, []).append(v)
+        lines = [f"# FP64 vector work of the constitutive kernels on the {workload} workload, mixed form",
+                 "# (serialised replay of two increments from the saved state, every dispatch)", "",
+                 "commands (repository root R, one MI355X):", COUNTER_RUNS.format(regex=SPECTRAL_REGEX), "",
+                 "flops per dispatch = 64 x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_ADD_F64 + SQ_INSTS_VALU_MUL_F64"
+                 " + SQ_INSTS_VALU_TRANS_F64) (all lanes active); SQ_INSTS_VALU_FLOPS_FP64 is the hardware's own count", ""]
+        for fam, cs in sorted(by.items()):
+            n = len(cs.get("SQ_INSTS_VALU_FMA_F64", []))
+            if not n:
+                continue
+            m = {c: float(np.mean(v)) for c, v in cs.items()}
+            fl = 64.0 * (2 * m.get("SQ_INSTS_VALU_FMA_F64", 0) + m.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                         m.get("SQ_INSTS_VALU_MUL_F64", 0) + m.get("SQ_INSTS_VALU_TRANS_F64", 0))
+            fp64_share = (m.get("SQ_INSTS_VALU_FMA_F64", 0) + m.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                          m.get("SQ_INSTS_VALU_MUL_F64", 0) + m.get("SQ_INSTS_VALU_TRANS_F64", 0)) / max(m.get("SQ_INSTS_VALU", 1), 1)
+            lines += [f"{fam}: {n} dispatches",
+                      f"  mean per dispatch: FMA_F64 {m.get('SQ_INSTS_VALU_FMA_F64', 0):.4g}, ADD_F64 {m.get('SQ_INSTS_VALU_ADD_F64', 0):.4g}, "
+                      f"MUL_F64 {m.get('SQ_INSTS_VALU_MUL_F64', 0):.4g}, TRANS_F64 {m.get('SQ_INSTS_VALU_TRANS_F64', 0):.4g}, "
+                      f"VALU {m.get('SQ_INSTS_VALU', 0):.4g} wave instructions; FLOPS_FP64 counter {m.get('SQ_INSTS_VALU_FLOPS_FP64', 0):.4g}",
+                      f"  FP64 share of the VALU instructions {fp64_share:.3f}",
+                      f"flops_per_launch_{fam} = {fl:.6g}", ""]
+        lines.append(f"source_digest = {source_digest(_CONST_SRC)}")
+        with open(os.path.join(profiles or os.path.join(ROOT, "profiles"), f"pmc_valu_constitutive_{workload}_mixed.txt"),
+                  "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        written.append(("constitutive", None))
+    print(json.dumps({"written": written}))
+
+
+def stored_flops(family: str, workload: str):
+    """FP64 flops per launch of a constitutive kernel from the committed VALU counter summary;
+    None when missing or the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_valu_constitutive_{workload}_mixed.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(rf"^flops_per_launch_{family}\s*=\s*([0-9.eE+]+)", text, re.M)
+    d = re.search(r"^source_digest\s*=\s*([0-9a-f]+)", text, re.M)
+    if not m or not d or d.group(1) != source_digest(_CONST_SRC):
+        return None
+    return float(m.group(1))
+
+
+TRACE_RUNS = """cd /tmp && export TMPDIR=/tmp && export RVE_WORKERS=1
+rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/trace_replay -o replay -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline > $R/gpurun_out/trace_replay.json
+python3 bench.py --summarize-trace gpurun_out --profiles-dir gpurun_out/summaries   (then copied to profiles/)"""
+def summarize_trace(out_dir, workload="sweep32", profiles=None):
+    """profiles/kernels_<workload>_mixed_replay.txt from the kernel trace of TRACE_RUNS: per
+    family, the dispatches after the replay marker, their total time, and the mean over the live
+    ones against the event-timed figures that the traced process printed.  A CG launch issued
+    after its solve converged reads the stop flag and returns within about 2 us; the event timer
+    knows how many launches were live, so the shortest (dispatches - live) dispatches of a family
+    are taken as its no-ops."""
+    import csv
+    import glob
+
+    import numpy as np
+
+    if profiles:
+        os.makedirs(profiles, exist_ok=True)
+    rows = []
+    for f in glob.glob(os.path.join(out_dir, "trace_replay", "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    # the replay follows the marker kernel that bench.py launches right before it
+    marks = [i for i, (_, _, n) in enumerate(rows) if "FillFunctor" in n]
+    if not marks:
+        raise SystemExit("no replay marker in the trace")
+    rows = rows[marks[-1] + 1:]
+    line = json.loads(open(os.path.join(out_dir, "trace_replay.json")).read().strip().splitlines()[-1])
+    roof = line["roofline"]
+    ev = {p["family"]: p for p in roof["spectral_kernels"] + roof.get("constitutive_kernels", [])}
+    names = _NAME_FAMILY + [(pat, f) for pat, f in CONST_FAMILIES]
+    dur = {}
+    for a, b, n in rows:
+        fam = next((f for pat, f in names if pat in n), None)
+        if fam:
+            dur.setdefault(fam, []).append((b - a) / 1e3)
+    inc = roof["replay_increments"]
+    out = [f"# Kernel durations of the serialised replay ({workload}, mixed form, increments {inc[0]}-{inc[1]},",
+           "# one RVE at a time, every RVE of the workload)", "",
+           "commands (repository root R, one MI355X):", TRACE_RUNS, "",
+           "per family: dispatches after the replay marker; live = those the event timer counted (the",
+           "shortest dispatches - live are the no-op launches past a converged CG solve); trace mean over",
+           "the live dispatches; the same launches timed with HIP events by the traced process; the",
+           "algorithmic bytes per launch and the HBM fraction from the trace's duration", "",
+           "family          dispatches   live  trace total ms  trace mean us  event mean us  noop max us  "
+           "live min us  MB/launch  trace frac"]
+    for fam in [f for f in SPECTRAL + tuple(f for _, f in CONST_FAMILIES) if f in dur]:
+        d = np.sort(np.array(dur[fam]))
+        e = ev.get(fam)
+        n_live = min(len(d), e["launches"]) if e else len(d)
+        noop, live = d[: len(d) - n_live], d[len(d) - n_live:]
+        mb = e.get("algorithmic_bytes_per_launch", 0) / 1e6 if e else 0
+        frac = mb * 1e6 / (live.mean() * 1e-6) / (HBM_PEAK_GBS * 1e9) if mb else float("nan")
+        out.append(f"{fam:15s} {len(d):10d} {n_live:6d} {d.sum() / 1e3:15.2f} {live.mean():14.2f} "
+                   f"{(e['avg_launch_us'] if e else float('nan')):14.2f} {(noop.max() if len(noop) else float('nan')):12.2f} "
+                   f"{live.min():12.2f} {mb:10.3f} {frac:11.3f}")
+    text = "\n".join(out) + "\n"
+    path = os.path.join(profiles or os.path.join(ROOT, "profiles"), f"kernels_{workload}_mixed_replay.txt")
+    with open(path, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
 def main():
+    global _ROCTX
     args = parse()
+    _ROCTX = _load_roctx()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload, args.profiles_dir)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload, args.profiles_dir)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (this build has no multi-GPU "
                                    "path); run it with --gpus 1"}))
@@ -389,8 +649,10 @@ def main():
         "config": config,
     }
     if not args.no_roofline:
-        fam, T = roofline_replay(lib, rves, path, state, W + 1, max(1, min(args.replay, K)), opts)
+        Rn = max(1, min(args.replay, K))
+        fam, T = roofline_replay(lib, rves, path, state, W + 1, Rn, opts)
         line["roofline"] = roofline(fam, T, args.workload)
+        line["roofline"]["replay_increments"] = [W + 1, W + Rn]
     del state
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, len(rves))

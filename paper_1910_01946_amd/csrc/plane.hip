@@ -54,6 +54,11 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* r
 // Threads per plane block: the plane transforms are a chain of dependent LDS stages, so
 // more threads per plane (fewer points each) shorten the chain.
 constexpr int kPlaneThreads = 512;
+// The three-component passes of the factorised projection launch a third of the blocks of the
+// nine-component ones; twice the threads per plane halve each thread's share of the chain.
+constexpr int kPlane3Threads = 1024;
+template <bool THREE>
+constexpr int plane_threads() { return THREE ? kPlane3Threads : kPlaneThreads; }
 
 // Source of the factorised projection's forward pass: row i of the divergence stencil,
 // v_i = sum_l D_l^H y_il with D_l^H = 1/4 (S_l^-1 - 1) prod_{m != l} (1 + S_m^-1), at plane z,
@@ -144,9 +149,9 @@ __device__ __forceinline__ void plane_divergence(const GridPlan& g, const PlaneA
 }
 
 template <typename T, int SRC, int PPT, int RS>
-__global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneArgs a, CGState* cg) {
+__global__ void __launch_bounds__(plane_threads<SRC == PF_DIV>()) k_plane_fwd(GridPlan g, PlaneArgs a, CGState* cg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[8];
+  __shared__ double red[16];
   if (cg) {
     if (cg->done) return;
     // beta step of this iteration (one block; the others only read the stop flag, and a
@@ -222,9 +227,9 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd(GridPlan g, PlaneAr
 }
 
 template <typename T, int MODE, int PPT, int RS>
-__global__ void __launch_bounds__(kPlaneThreads) k_plane_inv(GridPlan g, PlaneInvArgs a) {
+__global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv(GridPlan g, PlaneInvArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[8];
+  __shared__ double red[16];
   if (MODE == PI_CG && a.cg->done) return;
   if (MODE == PI_OUT_T && a.cg && a.cg->done) return;
   const int c = blockIdx.x, z = blockIdx.y;
@@ -555,9 +560,9 @@ static size_t plane_lds(const GridPlan& g, bool fp32) {
   return cs * (npair * padded_len(g.nx) + (size_t)skewed_line(g.nxh, padded_len(g.ny)) + g.nx + g.ny);
 }
 
-static int plane_ppt(const GridPlan& g) {
+static int plane_ppt(const GridPlan& g, int threads = kPlaneThreads) {
   const int npts = std::max(((g.ny + 1) / 2) * g.nx, g.nxh * g.ny);
-  return (npts + kPlaneThreads - 1) / kPlaneThreads;
+  return (npts + threads - 1) / threads;
 }
 
 bool plane_fits(const GridPlan& g, bool fp32) { return plane_lds(g, fp32) <= 159 * 1024 && plane_ppt(g) <= 33; }
@@ -581,7 +586,7 @@ static hipError_t plane_limits_rs(int bytes) {
   if ((f = lds_limit(k_plane_inv<T, PI_CG, PPT, RS>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_plane_inv<T, PI_RESID, PPT, RS>, bytes)) != hipSuccess) e = f;
   if ((f = lds_limit(k_plane_inv<T, PI_OUT64, PPT, RS>, bytes)) != hipSuccess) e = f;
-  if constexpr (PPT <= 17) {
+  if constexpr (PPT <= 9) {
     if ((f = lds_limit(k_plane_fwd<T, PF_DIV, PPT, RS>, bytes)) != hipSuccess) e = f;
     if ((f = lds_limit(k_plane_inv<T, PI_OUT_T, PPT, RS>, bytes)) != hipSuccess) e = f;
   }
@@ -623,8 +628,8 @@ static int plane_radix_set(const GridPlan& g) { return radix_set_for(radix_bits(
 template <typename T, int SRC, int PPT, int RS>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(SRC == PF_DIV ? 3 : 9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st, g,
-         a, cg);
+  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(SRC == PF_DIV ? 3 : 9, g.nz), dim3(plane_threads<SRC == PF_DIV>()),
+         (uint32_t)sh, st, g, a, cg);
 }
 
 template <typename T, int SRC, int PPT>
@@ -639,20 +644,18 @@ static void fwd_dispatch_rs(const GridPlan& g, const PlaneArgs& a, CGState* cg, 
 
 template <typename T, int SRC>
 static void fwd_dispatch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
-  const int ppt = plane_ppt(g);
+  const int ppt = plane_ppt(g, plane_threads<SRC == PF_DIV>());
   if constexpr (SRC == PF_DIV) {
-    // compiled to 17 points per thread (factorised_fits)
+    // compiled to 9 points per thread of 1024 (factorised_fits)
     if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
-    else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
-    else if (plane_radix_set(g) == (RS_8 | RS_2)) fwd_launch<T, SRC, 17, RS_8 | RS_2>(g, a, cg, st);
-    else fwd_launch<T, SRC, 17, RS_ALL>(g, a, cg, st);
-    return;
-  }
+    else fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
+  } else {
   if (ppt <= 5) fwd_dispatch_rs<T, SRC, 5>(g, a, cg, st);
   else if (ppt <= 9) fwd_dispatch_rs<T, SRC, 9>(g, a, cg, st);
   else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) fwd_launch<T, SRC, 17, RS_8 | RS_2>(g, a, cg, st);
   else if (ppt <= 17) fwd_launch<T, SRC, 17, RS_ALL>(g, a, cg, st);
   else fwd_launch<T, SRC, 33, RS_ALL>(g, a, cg, st);
+  }
 }
 
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st) {
@@ -672,8 +675,8 @@ void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState*
 template <typename T, int MODE, int PPT, int RS>
 static void inv_launch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_inv<T, MODE, PPT, RS>, dim3(MODE == PI_OUT_T ? 3 : 9, g.nz), dim3(kPlaneThreads), (uint32_t)sh, st,
-         g, a);
+  launch(k_plane_inv<T, MODE, PPT, RS>, dim3(MODE == PI_OUT_T ? 3 : 9, g.nz), dim3(plane_threads<MODE == PI_OUT_T>()),
+         (uint32_t)sh, st, g, a);
 }
 
 template <typename T, int MODE, int PPT>
@@ -688,19 +691,17 @@ static void inv_dispatch_rs(const GridPlan& g, const PlaneInvArgs& a, hipStream_
 
 template <typename T, int MODE>
 static void inv_dispatch(const GridPlan& g, const PlaneInvArgs& a, hipStream_t st) {
-  const int ppt = plane_ppt(g);
+  const int ppt = plane_ppt(g, plane_threads<MODE == PI_OUT_T>());
   if constexpr (MODE == PI_OUT_T) {
     if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
-    else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
-    else if (plane_radix_set(g) == (RS_8 | RS_2)) inv_launch<T, MODE, 17, RS_8 | RS_2>(g, a, st);
-    else inv_launch<T, MODE, 17, RS_ALL>(g, a, st);
-    return;
-  }
+    else inv_dispatch_rs<T, MODE, 9>(g, a, st);
+  } else {
   if (ppt <= 5) inv_dispatch_rs<T, MODE, 5>(g, a, st);
   else if (ppt <= 9) inv_dispatch_rs<T, MODE, 9>(g, a, st);
   else if (ppt <= 17 && plane_radix_set(g) == (RS_8 | RS_2)) inv_launch<T, MODE, 17, RS_8 | RS_2>(g, a, st);
   else if (ppt <= 17) inv_launch<T, MODE, 17, RS_ALL>(g, a, st);
   else inv_launch<T, MODE, 33, RS_ALL>(g, a, st);
+  }
 }
 
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st) {
@@ -719,7 +720,7 @@ void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipSt
 
 int plane_blocks(const GridPlan& g) { return 9 * g.nz; }
 
-bool factorised_fits(const GridPlan& g) { return g.freq == FREQ_ROTATED && plane_ppt(g) <= 17; }
+bool factorised_fits(const GridPlan& g) { return g.freq == FREQ_ROTATED && plane_ppt(g, kPlane3Threads) <= 9; }
 
 // Columns of 256 threads over the plane, z chunks of lz planes: the smallest lz that keeps
 // the grid (and the p.q partials) at 1024 blocks.

@@ -342,7 +342,12 @@ static TunedTiles tuned_tz(const int n[3], bool fp32) {
   return TunedTiles{};
 }
 
-static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false, int freq = FREQ_ROTATED) {
+// st: the stream that uploads the tables (stream-ordered, then synchronised).  Plans built
+// while other threads may be capturing CG graphs (a worker's first FP64 use) must pass their
+// RVE's stream: a synchronous copy runs on the legacy stream, which a capture in progress on
+// another stream forbids.
+static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false, int freq = FREQ_ROTATED,
+                       hipStream_t st = nullptr) {
   GridPlan& g = P.g;
   const TunedTiles tt = autotune ? tuned_tz(n, fp32) : TunedTiles{};
   plan_geometry(g, n, tt.tz, tt.tz3);
@@ -363,17 +368,25 @@ static void build_plan(Plan& P, const int n[3], bool fp32, bool autotune = false
       E[2 * k] = c;
       E[2 * k + 1] = s;
     }
+    auto put = [&](void* dst, const void* src, size_t bytes) {
+      if (st) {
+        HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipStreamSynchronize(st));  // the host vectors end with this iteration
+      } else {
+        HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+      }
+    };
     if (fp32) {
       std::vector<float> twf(2 * m);
       for (int i = 0; i < 2 * m; ++i) twf[i] = (float)tw[i];
       P.tw[d].alloc(sizeof(float) * 2 * m);
-      HIPCHECK(hipMemcpy(P.tw[d].p, twf.data(), sizeof(float) * 2 * m, hipMemcpyHostToDevice));
+      put(P.tw[d].p, twf.data(), sizeof(float) * 2 * m);
     } else {
       P.tw[d].alloc(sizeof(double) * 2 * m);
-      HIPCHECK(hipMemcpy(P.tw[d].p, tw.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice));
+      put(P.tw[d].p, tw.data(), sizeof(double) * 2 * m);
     }
     P.E[d].alloc(sizeof(double) * 2 * m);
-    HIPCHECK(hipMemcpy(P.E[d].p, E.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice));
+    put(P.E[d].p, E.data(), sizeof(double) * 2 * m);
   }
   g.twx = P.tw[0].p;
   g.twy = P.tw[1].p;
@@ -599,7 +612,7 @@ static Work& work(RVE& R, bool fp32) {
   Work& w = R.w[fp32 ? 1 : 0];
   if (!w.ready) {
     w.fp32 = fp32;
-    build_plan(w.plan, R.n, fp32, R.autotune, R.freq);
+    build_plan(w.plan, R.n, fp32, R.autotune, R.freq, R.stream);
     const int64_t nv = R.nvox;
     const size_t ts = tsize(fp32);
     // grouped layout: G groups of W entries per voxel (see tangent_index)
@@ -622,6 +635,8 @@ static Work& work(RVE& R, bool fp32) {
   w.k16 = fp32 && w.plane && tangent16_enabled();
   return w;
 }
+
+static void prepare_correction(RVE& R);
 
 static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   for (int i = 0; i < 3; ++i) R.n[i] = d.n[i];
@@ -688,6 +703,7 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
   HIPCHECK(hipHostMalloc((void**)&R.host_poll, 2 * sizeof(CGState), hipHostMallocDefault));
   for (hipEvent_t& e : R.poll_ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   Work& w = work(R, C.fp32);
+  if (C.fp32) prepare_correction(R);
   R.cg.alloc(sizeof(CGState));
   HIPCHECK(hipMemset(R.cg.p, 0, sizeof(CGState)));
   const int nb = std::max(std::max(xfwd_blocks(w.plan.g), 1024), std::max(9 * R.n[2], 2048));
@@ -805,14 +821,18 @@ static void project_field(const GridPlan& g, bool fp32, bool plane, void* spec, 
 // compatible field; the correction is therefore widened to FP64 and projected again,
 // G(x) with the same zero-frequency rule (F-controlled averages stay fixed), so that
 // F - <F> stays a discrete gradient to FP64 rounding.
+// The FP64 projection's plan and buffers (set up at rve_create for mixed handles).
+static void prepare_correction(RVE& R) {
+  if (R.proj_ready) return;
+  build_plan(R.proj_plan, R.n, false, R.autotune, R.freq, R.stream);
+  R.proj_spec.alloc(tsize(false) * 2 * 9 * R.proj_plan.g.nspec);
+  R.x64.alloc(sizeof(double) * 9 * (size_t)R.nvox);
+  R.proj_ready = true;
+}
+
 static const double* newton_correction(RVE& R, Work& w, const void* x, const double* keep) {
   if (!w.fp32) return static_cast<const double*>(x);
-  if (!R.proj_ready) {
-    build_plan(R.proj_plan, R.n, false, R.autotune, R.freq);
-    R.proj_spec.alloc(tsize(false) * 2 * 9 * R.proj_plan.g.nspec);
-    R.x64.alloc(sizeof(double) * 9 * (size_t)R.nvox);
-    R.proj_ready = true;
-  }
+  prepare_correction(R);
   double* x64 = R.x64.as<double>();
   launch_widen(static_cast<const float*>(x), x64, 9 * R.nvox, R.stream);
   const GridPlan& g = R.proj_plan.g;
@@ -1776,6 +1796,9 @@ int32_t rve_step_increment(rve_handle h, const double* F_bar, const uint8_t* mas
     std::vector<rve_step_stats> st(nr);
     std::vector<int32_t> rcs(nr, RVE_OK);
     std::vector<std::string> msgs(nr);
+    // the workers take the RVEs in the handle's order (on the mixed-size sweep this beat
+    // longest-first, shortest-first and alternating orders: a tail of small RVEs alone leaves
+    // the GPU idle, and a block of large ones at the start does too little with the rest)
     std::atomic<int> next(0);
     auto worker = [&]() {
       (void)hipSetDevice(h->device);

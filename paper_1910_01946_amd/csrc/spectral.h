@@ -255,8 +255,9 @@ hipError_t set_plane_lds_limits(int bytes);
 int plane_blocks(const GridPlan& g);
 int prep_blocks(const GridPlan& g);
 // The factorised projection runs with the rotated scheme only, on grids that take the plane
-// path and whose planes have at most 17 points per thread of the plane kernels (planes to
-// about 128 x 128); the caller checks plane_fits for its precision.
+// path and whose planes have at most 9 points per thread of the 1024-thread three-component
+// plane kernels (planes to about 128 x 128, all that the plane path holds in LDS); the caller
+// checks plane_fits for its precision.
 bool factorised_fits(const GridPlan& g);
 int grad_blocks(const GridPlan& g, int lz);
 int grad_lz(const GridPlan& g);

@@ -359,6 +359,25 @@ def test_batch_of_uneven_rves_equals_separate_handles(lib):
     assert np.array_equal(hb.field("rho_gnd", 1), hs.field("rho_gnd", 0))
 
 
+def test_mixed_batch_with_graphs_on_concurrent_workers(lib):
+    """Sixteen mixed-form RVEs on eight host workers with CG graphs: every RVE's first increment
+    (when each worker captures its graphs while others start their solves) and the next one
+    succeed, and the result equals the same handle driven by one worker without graphs."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    rves = [synth.voronoi_rve(600 + i, (16, 16, 16), 6, 2e-6, mat) for i in range(16)]
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    out = {}
+    for workers, graph in ((8, 1), (1, 0)):
+        h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3, use_graph=graph,
+                            workers=workers)
+        for k in (1, 2):
+            st = h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+            assert all(s["status"] == 0 and s["fp64_fallback"] == 0 for s in st)
+        out[workers] = np.array([h.macro(i)[0] for i in range(len(rves))])
+        h.close()
+    assert np.array_equal(out[8], out[1])
+
+
 def test_kernel_timing_counts_live_launches(lib):
     rves, path = synth.workload("cu16", n_override=8, n_inc_override=20)
     h = lib.Homogenizer(rves, precision=lib.RVE_MIXED, newton_tol=1e-6, cg_tol=1e-3)
