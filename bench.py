@@ -96,6 +96,7 @@ def parse():
     ap.add_argument("--rves", type=int, default=None, help="use only the first R RVEs of the workload")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--profiles-dir", default=None, help="where the summaries go (default: profiles/)")
+    ap.add_argument("--bench-json", default=None, help="an unprofiled bench line to compare with (--summarize-trace)")
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
                     help="write profiles/kernels_* from the kernel trace under DIR (see TRACE_RUNS)")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
@@ -189,14 +190,15 @@ def source_digest(files):
 
 
 def stored_traffic(family: str, workload: str, precision: str):
-    """HBM bytes per launch from the committed counter summary of this kernel and workload
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy); None when the
-    summary is missing or the kernel's sources changed since the counters were taken."""
+    """Ratio of measured HBM bytes (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
+    plain copy) to algorithmic bytes per launch, from the committed counter summary of this kernel
+    and workload; None when the summary is missing or the kernel's sources changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", f"pmc_{family}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"^traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", text, re.M)
+    m = re.search(r"^traffic_ratio\s*=\s*([0-9.eE+]+)", text, re.M)
     d = re.search(r"^source_digest\s*=\s*([0-9a-f]+)", text, re.M)
     if not m or not d or d.group(1) != source_digest(FAMILY_KERNELS[family][1]):
         return None
@@ -299,7 +301,12 @@ def roofline(fam, T, workload):
                     "launches": n,
                     "avg_launch_us": 1e3 * ms / n, "algorithmic_bytes_per_launch": units / n,
                     "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "share": round(share[f], 4),
-                    "traffic": stored_traffic(f, workload, "mixed")})
+                    "traffic": None})
+        ratio = stored_traffic(f, workload, "mixed")
+        if ratio is not None:
+            # measured / algorithmic bytes from the counter sample, applied to this replay's launches
+            per[-1]["traffic"] = ratio * units / n
+            per[-1]["traffic_ratio"] = ratio
     dom = max(share, key=share.get)
     out = {"kernel": FAMILY_KERNELS[dom][0], "family": dom,
            "share_of_serialised_replay": {f: round(v, 4) for f, v in share.items()}}
@@ -322,10 +329,14 @@ def roofline(fam, T, workload):
         n, ms, units = fam[f]
         if n == 0:
             continue
-        fl = stored_flops(f, workload)
-        ach = fl * n / (ms * 1e-3) / 1e12 if fl else None
+        # the continuation pass works through a data-dependent list with a fixed grid: no flops per
+        # voxel apply to it
+        fpv = stored_flops(f, workload) if f != "slip_slow" else None
+        # units: voxels per launch (the listed voxels for the continuation pass)
+        ach = fpv * units / (ms * 1e-3) / 1e12 if fpv else None
         cons.append({"family": f, "kernel": FAMILY_KERNELS[f][0], "bound": "alu", "launches": n,
-                     "avg_launch_us": 1e3 * ms / n, "flops_per_launch": fl, "achieved": ach,
+                     "avg_launch_us": 1e3 * ms / n, "flops_per_voxel": fpv, "voxels_per_launch": units / n,
+                     "achieved": ach,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach / FP64_PEAK_TFLOPS if ach else None, "share": round(share[f], 4)})
     out["constitutive_kernels"] = cons
@@ -355,13 +366,17 @@ def copy_calibration():
 COUNTER_RUNS = """cd /tmp && export TMPDIR=/tmp && export RVE_WORKERS=1
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_f -o c -- python3 $R/bench.py --copy-calibration
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_w -o c -- python3 $R/bench.py --copy-calibration
-rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_f -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline
-rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_w -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline > $R/gpurun_out/pmc_w_bench.json
-rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU SQ_BUSY_CYCLES --kernel-include-regex "FillFunctor|k_slip_fast|k_slip_slow|k_stress_tangent" --output-format csv -d $R/gpurun_out/pmc_valu -o m -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline
+rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_f -o m -- python3 $R/bench.py {sample} --no-fp64-compare --no-cpu-baseline
+rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "{regex}" --output-format csv -d $R/gpurun_out/pmc_w -o m -- python3 $R/bench.py {sample} --no-fp64-compare --no-cpu-baseline > $R/gpurun_out/pmc_w_bench.json
+rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU SQ_BUSY_CYCLES --kernel-include-regex "FillFunctor|k_slip_fast|k_slip_slow|k_stress_tangent" --output-format csv -d $R/gpurun_out/pmc_valu -o m -- python3 $R/bench.py {sample} --no-fp64-compare --no-cpu-baseline
 python3 bench.py --summarize-counters gpurun_out --profiles-dir gpurun_out/summaries   (then copied to profiles/)"""
 CONST_FAMILIES = (("k_slip_fast", "slip_fast"), ("k_slip_slow", "slip_slow"), ("k_stress_tangent<", "stress_tangent"))
 FP64_PEAK_TFLOPS = 78.6
 SPECTRAL_REGEX = "FillFunctor|k_cg_prep|k_plane_fwd|k_mid|k_plane_inv|k_cg_grad"
+# Counter collection serialises every dispatch: the counter runs take a sample of the workload
+# (its first four RVEs, the same warmup, one replayed increment), and the summaries keep the ratio of
+# measured to algorithmic bytes, which the bench applies to its own replay's launches.
+COUNTER_SAMPLE = "--rves 4 --warmup 5 --steps 1 --replay 1"
 # template arguments that tell the spectral families apart in the demangled kernel names
 # (PF_F64 = 1, PF_DIV = 3; MID_GREEN = 0, MID_GREEN3 = 2; PI_RESID = 1, PI_OUT_T = 3)
 _NAME_FAMILY = [(r"k_cg_prep<float, 1, 0>", "cg_prep"), (r"k_plane_fwd<float, 3,", "plane_div"),
@@ -370,7 +385,7 @@ _NAME_FAMILY = [(r"k_cg_prep<float, 1, 0>", "cg_prep"), (r"k_plane_fwd<float, 3,
                 (r"k_cg_grad<float>", "cg_grad")]
 
 
-def _counter_rows(directory, after_marker=True):
+def _counter_rows(directory, after_marker=True, with_grid=False):
     """(kernel name, counter, value) of the dispatches in the rocprofv3 CSV files under directory;
     with after_marker, only those after the last replay marker (the fill kernel that bench.py
     launches right before its serialised replay)."""
@@ -382,14 +397,15 @@ def _counter_rows(directory, after_marker=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
                 did = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0)
-                rows.append((did, r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+                rows.append((did, r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]),
+                             int(float(r.get("Grid_Size") or 0))))
     rows.sort(key=lambda t: t[0])
     if after_marker:
-        marks = [d for d, n, _, _ in rows if "FillFunctor" in n]
+        marks = [r[0] for r in rows if "FillFunctor" in r[1]]
         if not marks:
             raise SystemExit(f"no replay marker among the dispatches under {directory}")
         rows = [r for r in rows if r[0] > max(marks)]
-    return [(n, c, v) for _, n, c, v in rows]
+    return [r[1:] if with_grid else r[1:4] for r in rows]
 
 
 def summarize_counters(out_dir, workload="sweep32", profiles=None):
@@ -430,11 +446,11 @@ def summarize_counters(out_dir, workload="sweep32", profiles=None):
         a = alg[fam]
         traffic = (f_mb + w_mb) * 1e6
         text = f"""# HBM traffic of {a['instantiation']} on the {workload} workload, mixed form
-# (serialised replay of two increments from the saved state: every RVE of the workload, one at
-# a time, grids of several sizes; per-launch figures are averages over the live launches)
+# (counter sample: {COUNTER_SAMPLE}, serialised, one RVE at a time; per-launch figures are averages
+# over the live launches of the replayed increment)
 
 commands (repository root R, one MI355X), one counter per run:
-{COUNTER_RUNS.format(regex=SPECTRAL_REGEX)}
+{COUNTER_RUNS.format(regex=SPECTRAL_REGEX, sample=COUNTER_SAMPLE)}
 
 calibration: a device copy of 2^30 bytes, 5 dispatches
   FETCH_SIZE {kib_f:.1f} KiB per dispatch for 1048576 KiB read     -> scale {s_f:.5f}
@@ -446,6 +462,7 @@ calibration: a device copy of 2^30 bytes, 5 dispatches
   algorithmic bytes per launch (bench line of the WRITE_SIZE run): {a['algorithmic_bytes_per_launch'] / 1e6:.3f} MB; measured / algorithmic = {traffic / a['algorithmic_bytes_per_launch']:.2f}
 
 traffic_bytes_per_launch = {traffic:.0f}
+traffic_ratio = {traffic / a['algorithmic_bytes_per_launch']:.4f}
 source_digest = {source_digest(FAMILY_KERNELS[fam][1])}
 """
         path = os.path.join(profiles or os.path.join(ROOT, "profiles"), f"pmc_{fam}_{workload}_mixed.txt")
@@ -454,18 +471,22 @@ source_digest = {source_digest(FAMILY_KERNELS[fam][1])}
         written.append((fam, traffic / a["algorithmic_bytes_per_launch"]))
     # FP64 vector work of the constitutive kernels: 64 lanes x (2 FMA + ADD + MUL + TRANS) per
     # wave instruction (no MFMA on this path), per dispatch
-    vrows = _counter_rows(os.path.join(out_dir, "pmc_valu"))
+    vrows = _counter_rows(os.path.join(out_dir, "pmc_valu"), with_grid=True)
     if vrows:
-        by = {}
-        for name, c, v in vrows:
+        by, grid = {}, {}
+        for name, c, v, gs in vrows:
             fam = next((f for pat, f in CONST_FAMILIES if pat in name), None)
             if fam:
                 by.setdefault(fam, {}).setdefault(c, []).append(v)
+                if c == "SQ_INSTS_VALU_FMA_F64":
+                    grid.setdefault(fam, []).append(gs)
         lines = [f"# FP64 vector work of the constitutive kernels on the {workload} workload, mixed form",
                  "# (serialised replay of two increments from the saved state, every dispatch)", "",
-                 "commands (repository root R, one MI355X):", COUNTER_RUNS.format(regex=SPECTRAL_REGEX), "",
+                 "commands (repository root R, one MI355X):", COUNTER_RUNS.format(regex=SPECTRAL_REGEX, sample=COUNTER_SAMPLE), "",
                  "flops per dispatch = 64 x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_ADD_F64 + SQ_INSTS_VALU_MUL_F64"
-                 " + SQ_INSTS_VALU_TRANS_F64) (all lanes active); SQ_INSTS_VALU_FLOPS_FP64 is the hardware's own count", ""]
+                 " + SQ_INSTS_VALU_TRANS_F64) (all lanes active); SQ_INSTS_VALU_FLOPS_FP64 is the hardware's own count;",
+                 "flops per voxel = flops per dispatch / threads per dispatch (one voxel per thread; k_slip_slow",
+                 "runs a fixed grid over the list of voxels the first pass left, so its figure is per grid thread)", ""]
         for fam, cs in sorted(by.items()):
             n = len(cs.get("SQ_INSTS_VALU_FMA_F64", []))
             if not n:
@@ -475,12 +496,17 @@ source_digest = {source_digest(FAMILY_KERNELS[fam][1])}
                          m.get("SQ_INSTS_VALU_MUL_F64", 0) + m.get("SQ_INSTS_VALU_TRANS_F64", 0))
             fp64_share = (m.get("SQ_INSTS_VALU_FMA_F64", 0) + m.get("SQ_INSTS_VALU_ADD_F64", 0) +
                           m.get("SQ_INSTS_VALU_MUL_F64", 0) + m.get("SQ_INSTS_VALU_TRANS_F64", 0)) / max(m.get("SQ_INSTS_VALU", 1), 1)
+            fpv = float(np.sum([64.0 * (2 * a + b + c + d) for a, b, c, d in zip(
+                cs.get("SQ_INSTS_VALU_FMA_F64", []), cs.get("SQ_INSTS_VALU_ADD_F64", [0] * n),
+                cs.get("SQ_INSTS_VALU_MUL_F64", [0] * n), cs.get("SQ_INSTS_VALU_TRANS_F64", [0] * n))])
+                        / max(float(np.sum(grid.get(fam, [1]))), 1.0))
             lines += [f"{fam}: {n} dispatches",
                       f"  mean per dispatch: FMA_F64 {m.get('SQ_INSTS_VALU_FMA_F64', 0):.4g}, ADD_F64 {m.get('SQ_INSTS_VALU_ADD_F64', 0):.4g}, "
                       f"MUL_F64 {m.get('SQ_INSTS_VALU_MUL_F64', 0):.4g}, TRANS_F64 {m.get('SQ_INSTS_VALU_TRANS_F64', 0):.4g}, "
                       f"VALU {m.get('SQ_INSTS_VALU', 0):.4g} wave instructions; FLOPS_FP64 counter {m.get('SQ_INSTS_VALU_FLOPS_FP64', 0):.4g}",
                       f"  FP64 share of the VALU instructions {fp64_share:.3f}",
-                      f"flops_per_launch_{fam} = {fl:.6g}", ""]
+                      f"flops_per_launch_{fam} = {fl:.6g}",
+                      f"flops_per_voxel_{fam} = {fpv:.6g}", ""]
         lines.append(f"source_digest = {source_digest(_CONST_SRC)}")
         with open(os.path.join(profiles or os.path.join(ROOT, "profiles"), f"pmc_valu_constitutive_{workload}_mixed.txt"),
                   "w") as fh:
@@ -490,13 +516,13 @@ source_digest = {source_digest(FAMILY_KERNELS[fam][1])}
 
 
 def stored_flops(family: str, workload: str):
-    """FP64 flops per launch of a constitutive kernel from the committed VALU counter summary;
-    None when missing or the kernel's sources changed since the counters were taken."""
+    """FP64 flops per voxel of a constitutive kernel's launch from the committed VALU counter
+    summary; None when missing or the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"pmc_valu_constitutive_{workload}_mixed.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(rf"^flops_per_launch_{family}\s*=\s*([0-9.eE+]+)", text, re.M)
+    m = re.search(rf"^flops_per_voxel_{family}\s*=\s*([0-9.eE+]+)", text, re.M)
     d = re.search(r"^source_digest\s*=\s*([0-9a-f]+)", text, re.M)
     if not m or not d or d.group(1) != source_digest(_CONST_SRC):
         return None
@@ -505,8 +531,8 @@ def stored_flops(family: str, workload: str):
 
 TRACE_RUNS = """cd /tmp && export TMPDIR=/tmp && export RVE_WORKERS=1
 rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/trace_replay -o replay -- python3 $R/bench.py --steps 1 --warmup 5 --replay 2 --no-fp64-compare --no-cpu-baseline > $R/gpurun_out/trace_replay.json
-python3 bench.py --summarize-trace gpurun_out --profiles-dir gpurun_out/summaries   (then copied to profiles/)"""
-def summarize_trace(out_dir, workload="sweep32", profiles=None):
+python3 bench.py --summarize-trace gpurun_out --profiles-dir gpurun_out/summaries --bench-json gpurun_out/bench.json   (bench.json: the unprofiled default run; then copied to profiles/)"""
+def summarize_trace(out_dir, workload="sweep32", profiles=None, bench_json=None):
     """profiles/kernels_<workload>_mixed_replay.txt from the kernel trace of TRACE_RUNS: per
     family, the dispatches after the replay marker, their total time, and the mean over the live
     ones against the event-timed figures that the traced process printed.  A CG launch issued
@@ -534,6 +560,12 @@ def summarize_trace(out_dir, workload="sweep32", profiles=None):
     line = json.loads(open(os.path.join(out_dir, "trace_replay.json")).read().strip().splitlines()[-1])
     roof = line["roofline"]
     ev = {p["family"]: p for p in roof["spectral_kernels"] + roof.get("constitutive_kernels", [])}
+    # the same replay timed by an unprofiled bench run (the tracer slows the traced process's
+    # own event timing by several us per launch)
+    ub = {}
+    if bench_json:
+        r2 = json.loads(open(bench_json).read().strip().splitlines()[-1])["roofline"]
+        ub = {p["family"]: p for p in r2["spectral_kernels"] + r2.get("constitutive_kernels", [])}
     names = _NAME_FAMILY + [(pat, f) for pat, f in CONST_FAMILIES]
     dur = {}
     for a, b, n in rows:
@@ -546,10 +578,11 @@ def summarize_trace(out_dir, workload="sweep32", profiles=None):
            "commands (repository root R, one MI355X):", TRACE_RUNS, "",
            "per family: dispatches after the replay marker; live = those the event timer counted (the",
            "shortest dispatches - live are the no-op launches past a converged CG solve); trace mean over",
-           "the live dispatches; the same launches timed with HIP events by the traced process; the",
-           "algorithmic bytes per launch and the HBM fraction from the trace's duration", "",
-           "family          dispatches   live  trace total ms  trace mean us  event mean us  noop max us  "
-           "live min us  MB/launch  trace frac"]
+           "the live dispatches; the same launches timed with HIP events by the traced process and by an",
+           "unprofiled bench run (bench mean); the algorithmic bytes per launch and the HBM fraction from",
+           "the trace's duration", "",
+           "family          dispatches   live  trace total ms  trace mean us  event mean us  bench mean us  "
+           "noop max us  live min us  MB/launch  trace frac"]
     for fam in [f for f in SPECTRAL + tuple(f for _, f in CONST_FAMILIES) if f in dur]:
         d = np.sort(np.array(dur[fam]))
         e = ev.get(fam)
@@ -557,8 +590,10 @@ def summarize_trace(out_dir, workload="sweep32", profiles=None):
         noop, live = d[: len(d) - n_live], d[len(d) - n_live:]
         mb = e.get("algorithmic_bytes_per_launch", 0) / 1e6 if e else 0
         frac = mb * 1e6 / (live.mean() * 1e-6) / (HBM_PEAK_GBS * 1e9) if mb else float("nan")
+        b = ub.get(fam)
         out.append(f"{fam:15s} {len(d):10d} {n_live:6d} {d.sum() / 1e3:15.2f} {live.mean():14.2f} "
-                   f"{(e['avg_launch_us'] if e else float('nan')):14.2f} {(noop.max() if len(noop) else float('nan')):12.2f} "
+                   f"{(e['avg_launch_us'] if e else float('nan')):14.2f} {(b['avg_launch_us'] if b else float('nan')):14.2f} "
+                   f"{(noop.max() if len(noop) else float('nan')):12.2f} "
                    f"{live.min():12.2f} {mb:10.3f} {frac:11.3f}")
     text = "\n".join(out) + "\n"
     path = os.path.join(profiles or os.path.join(ROOT, "profiles"), f"kernels_{workload}_mixed_replay.txt")
@@ -575,7 +610,7 @@ def main():
         summarize_counters(args.summarize_counters, args.workload, args.profiles_dir)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.workload, args.profiles_dir)
+        summarize_trace(args.summarize_trace, args.workload, args.profiles_dir, args.bench_json)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (this build has no multi-GPU "

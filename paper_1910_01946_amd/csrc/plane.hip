@@ -161,7 +161,20 @@ __global__ void __launch_bounds__(plane_threads<SRC == PF_DIV>()) k_plane_fwd(Gr
       if (threadIdx.x == 0) cg_beta_update(cg, rr, a.it == 0);
     }
   }
-  const int c = blockIdx.x, z = blockIdx.y;
+  int c, z;
+  if constexpr (SRC == PF_DIV) {
+    // XCD-aware order on a 1-D grid padded to a multiple of 8: consecutive hardware block ids
+    // go to the 8 XCDs in turn, and each XCD takes a contiguous run of (row, plane) in plane
+    // order, so that plane z - 1, which this block reads again, is still in that XCD's L2
+    const int nblk = 3 * g.nz, per = (nblk + 7) / 8;
+    const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (logical >= nblk) return;
+    c = logical / g.nz;
+    z = logical - c * g.nz;
+  } else {
+    c = blockIdx.x;
+    z = blockIdx.y;
+  }
   const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
   // A: npair packed rows (x lines), B: nxh columns (y lines), both padded (see padded());
   // the B lines are also skewed (see skewed_line()): the repack and the spectrum hand-off
@@ -628,8 +641,8 @@ static int plane_radix_set(const GridPlan& g) { return radix_set_for(radix_bits(
 template <typename T, int SRC, int PPT, int RS>
 static void fwd_launch(const GridPlan& g, const PlaneArgs& a, CGState* cg, hipStream_t st) {
   const size_t sh = plane_lds(g, sizeof(T) == 4);
-  launch(k_plane_fwd<T, SRC, PPT, RS>, dim3(SRC == PF_DIV ? 3 : 9, g.nz), dim3(plane_threads<SRC == PF_DIV>()),
-         (uint32_t)sh, st, g, a, cg);
+  const dim3 grid = SRC == PF_DIV ? dim3(8 * ((3 * g.nz + 7) / 8)) : dim3(9, g.nz);
+  launch(k_plane_fwd<T, SRC, PPT, RS>, grid, dim3(plane_threads<SRC == PF_DIV>()), (uint32_t)sh, st, g, a, cg);
 }
 
 template <typename T, int SRC, int PPT>

@@ -45,16 +45,19 @@ def run_sweep(rves, path, labels, precision=None, strains=(0.01, 0.05), rho_i=1.
     import paper_1910_01946_amd as lib
 
     prec = lib.RVE_MIXED if precision is None else precision
+    # time-step cut-back: at 0.1 % strain per increment the twins without the GND term (the
+    # lowest critical stresses) can take load steps that the local solve does not survive
     h = lib.Homogenizer(rves, precision=prec, newton_tol=1e-6, cg_tol=1e-3, max_cg=3000, max_newton=150,
-                        use_graph=1, autotune=1)
+                        use_graph=1, autotune=1, max_cutbacks=6)
     eps = [float(path.F_bar[k][0] - 1.0) for k in range(path.n_inc + 1)]
     curves = [[0.0] for _ in rves]
     t0 = time.perf_counter()
     for k in range(1, path.n_inc + 1):
-        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+        st = h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
         for i in range(len(rves)):
             curves[i].append(float(h.macro(i)[2][0]))   # Cauchy sigma_11
-        log(f"increment {k} done ({time.perf_counter() - t0:.1f} s)")
+        cuts = [i for i, s in enumerate(st) if s["cutbacks"]]
+        log(f"increment {k} done ({time.perf_counter() - t0:.1f} s)" + (f", cut back: RVEs {cuts}" if cuts else ""))
     h.close()
     out = {"strain": eps, "labels": [[m, d] for m, d in labels], "sigma_11": curves, "fits": {}}
     for m in sorted({m for m, _ in labels}):
