@@ -646,7 +646,7 @@ def main():
     config = {"workload": args.workload, "n_rve": len(rves), "voxels": nvox,
               "grids": sorted({tuple(r.n) for r in rves}), "increments_timed": [W + 1, W + K],
               "newton_tol": NEWTON_TOL, "cg_tol": CG_TOL, "precision": "mixed",
-              "batching": {"rves_per_handle": len(rves), "host_workers": 8, "streams": len(rves),
+              "batching": {"rves_per_handle": len(rves), "host_workers": int(os.environ.get("RVE_WORKERS", 8)), "streams": len(rves),
                            "cg_chunks_as_hip_graphs": not args.no_graph, "autotuned_z_tiles": not args.no_autotune},
               "per_increment": mixed["per_increment"],
               "discarded_voxel_iterations": mixed["discarded_vi"],

@@ -81,8 +81,10 @@ __global__ void k_roll_back(int nx, int ny, int nz, const double* in, double* ou
 
 // Sensitivity of the committed SSD densities (eqs. 8-9) to the similitude coefficient K and
 // the annihilation distance y_c at fixed slip increments: with S_a = sum_{b != a} (rho_SSD,b +
-// c_gnd rho_GND,b), 1/l_a = sqrt(S_a) / K and h_a = (1/b)(1/l_a - 2 y_c rho_SSD,a),
-//   d rho_a / dK = -|dg_a| sqrt(S_a) / (b K^2),   d rho_a / dy_c = -2 |dg_a| rho_SSD,a / b.
+// c_gnd rho_GND,b), u = |dg_a|, x = 2 y_c u / b and the update
+// rho_a = rho_SSD,a exp(-x) + u phi(x) sqrt(S_a) / (b K) (ssd_phi),
+//   d rho_a / dK = -u phi(x) sqrt(S_a) / (b K^2),
+//   d rho_a / dy_c = (2 u / b)(-rho_SSD,a exp(-x) + u sqrt(S_a) phi'(x) / (b K)).
 // Rows a (K) and 12 + a (y_c) of out; zero without hardening (the densities do not evolve).
 __global__ void k_density_sensitivity(int64_t nv, const MatDev* mat, const double* rho_ssd, const double* rho_gnd,
                                       const double* dg, double* out) {
@@ -99,9 +101,10 @@ __global__ void k_density_sensitivity(int64_t nv, const MatDev* mat, const doubl
   const double ib = 1.0 / M.burgers;
 #pragma unroll
   for (int a = 0; a < 12; ++a) {
-    const double w = M.hardening ? fabs(dg[a * nv + v]) * ib : 0.0;
-    out[a * nv + v] = -w * sqrt(tot - forest[a]) / (M.K_sim * M.K_sim);
-    out[(12 + a) * nv + v] = -2.0 * w * rs[a];
+    const double u = M.hardening ? fabs(dg[a * nv + v]) : 0.0;
+    const double x = 2.0 * M.y_c * u * ib, sq = sqrt(tot - forest[a]);
+    out[a * nv + v] = -u * ib * ssd_phi(x) * sq / (M.K_sim * M.K_sim);
+    out[(12 + a) * nv + v] = 2.0 * u * ib * (-rs[a] * exp(-x) + u * sq * ssd_dphi(x) * ib / M.K_sim);
   }
 }
 

@@ -191,13 +191,16 @@ __device__ int newton(const Point& p, double n, double tol, int maxit, double* d
     for (int a = 0; a < 12; ++a) d[a] = -R[a];
     lu12_solve(J, d);
     ++iters;
+    // fmax drops NaN operands, so finiteness is tested per component (a NaN compares false)
     double big = 0.0, xmax = 0.0;
+    bool finite = true;
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
+      finite = finite && fabs(d[a]) < 1e300;
       big = fmax(big, fabs(d[a]));
       xmax = fmax(xmax, fabs(dg[a]));
     }
-    if (!(big < 1e300)) return 0;  // non-finite step
+    if (!finite) return 0;  // non-finite step
     if (big > max_step) {
       const double s = max_step / big;
 #pragma unroll
@@ -663,8 +666,9 @@ __global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, Adj
     for (int i = 0; i < 9; ++i) Ab[i] = t[i] - Ab[i];
     double Fpnb[9];
     mtm3(k.A, Fpb, Fpnb);
-    // densities: rho_SSD = rho_n + h |dg| with h from the start-of-increment forest
-    double rn[12], rg[12], f[12], sq[12], h[12], tot = 0.0;
+    // densities: rho_SSD = rho_n exp(-x) + |dg| phi(x) sqrt(S) / (b K) with S the
+    // start-of-increment forest of the other systems, x = 2 y_c |dg| / b (ssd_phi)
+    double rn[12], rg[12], f[12], sq[12], h[12], ex[12], tot = 0.0;
     const bool hard = M.hardening != 0;
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
@@ -677,6 +681,7 @@ __global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, Adj
     for (int a = 0; a < 12; ++a) {
       sq[a] = sqrt(tot - f[a]);
       h[a] = hard ? (1.0 / M.burgers) * (sq[a] / M.K_sim - 2.0 * M.y_c * rn[a]) : 0.0;
+      ex[a] = exp(-2.0 * M.y_c * fabs(dg[a]) / M.burgers);
     }
     double mu[12];
 #pragma unroll
@@ -687,7 +692,7 @@ __global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, Adj
 #pragma unroll
         for (int j = 0; j < 3; ++j) s += kSlipS[a][i] * Ab[3 * i + j] * kSlipM[a][j];
       const double sg = dg[a] > 0.0 ? 1.0 : (dg[a] < 0.0 ? -1.0 : 0.0);
-      mu[a] = s + rb[a] * h[a] * sg;
+      mu[a] = s + rb[a] * h[a] * ex[a] * sg;   // d rho_a / d|dg_a| = h exp(-x)
     }
     // ---- 2. implicit function of the flow rule ----
     {
@@ -739,12 +744,15 @@ __global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, Adj
         double wsum = 0.0, wk[12];
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
-          const double w = rb[a] * fabs(dg[a]);
-          wk[a] = w / (2.0 * M.burgers * M.K_sim * sq[a]);
+          const double u = fabs(dg[a]), x = 2.0 * M.y_c * u / M.burgers;
+          const double w = rb[a] * u * ssd_phi(x);
+          wk[a] = w / (2.0 * M.burgers * M.K_sim * sq[a]);   // through sqrt(S_a)
           wsum += wk[a];
-          rnb[a] = rb[a] - w * 2.0 * M.y_c / M.burgers;
+          rnb[a] = rb[a] * ex[a];
           th[0] -= w * sq[a] / (M.burgers * M.K_sim * M.K_sim);
-          th[1] -= w * 2.0 * rn[a] / M.burgers;
+          // d rho / d y_c = (2 u / b)(-rho_n exp(-x) + u sqrt(S) phi'(x) / (b K))
+          th[1] += rb[a] * (2.0 * u / M.burgers) *
+                   (-rn[a] * ex[a] + u * sq[a] * ssd_dphi(x) / (M.burgers * M.K_sim));
         }
         const double mb2 = M.mu * M.burgers * M.mu * M.burgers;
 #pragma unroll
@@ -781,8 +789,9 @@ __global__ void __launch_bounds__(64) k_constitutive_adjoint(ConstArgs args, Adj
   }
 }
 
-// Commit of an increment: Fp = (R A_c R^T) Fp_n and rho_SSD = rho_SSD,n + h |dg| (eq. 8),
-// h = (1/b)(1/l - 2 y_c rho_SSD,n), l = K / sqrt(sum_{b != a} (rho_SSD,n + c_gnd rho_GND,n)).
+// Commit of an increment: Fp = (R A_c R^T) Fp_n and rho_SSD = rho_SSD,n + h |dg| phi(x) (eq. 8
+// integrated over the increment, see ssd_phi), h = (1/b)(1/l - 2 y_c rho_SSD,n),
+// l = K / sqrt(sum_{b != a} (rho_SSD,n + c_gnd rho_GND,n)), x = 2 y_c |dg| / b.
 __global__ void k_commit(CommitArgs args) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = args.nvox;
@@ -820,7 +829,8 @@ __global__ void k_commit(CommitArgs args) {
     for (int a = 0; a < 12; ++a) {
       const double ell = M.K_sim / sqrt(tot - forest[a]);
       const double h = (1.0 / M.burgers) * (1.0 / ell - 2.0 * M.y_c * rs[a]);
-      args.rho_ssd[a * nv + v] = rs[a] + h * fabs(dg[a]);
+      const double u = fabs(dg[a]);
+      args.rho_ssd[a * nv + v] = rs[a] + h * u * ssd_phi(2.0 * M.y_c * u / M.burgers);
     }
   }
 }

@@ -20,6 +20,19 @@ struct MatDev {
   int32_t screw_of[12];          // screw segment sharing the Burgers vector of each system
 };
 
+// The SSD density update (eq. 8) integrated exactly over one increment's slip u = |dg| with
+// the mean free path (eq. 9) frozen at its start-of-increment value:
+//   rho = rho_n exp(-x) + u phi(x) / (b l),  x = 2 y_c u / b,  phi(x) = (1 - exp(-x)) / x,
+// i.e. rho_n + h u phi(x) with h = (1/b)(1/l - 2 y_c rho_n) the forward-Euler rate.
+__device__ __forceinline__ double ssd_phi(double x) { return x > 0.0 ? -expm1(-x) / x : 1.0; }
+// phi'(x) = (exp(-x)(1 + x) - 1) / x^2; below x = 0.01 its Taylor series (the closed form
+// cancels there)
+__device__ __forceinline__ double ssd_dphi(double x) {
+  if (x < 0.01)
+    return -0.5 + x * (1.0 / 3.0 + x * (-1.0 / 8.0 + x * (1.0 / 30.0 + x * (-1.0 / 144.0 + x * (1.0 / 840.0)))));
+  return (exp(-x) * (1.0 + x) - 1.0) / (x * x);
+}
+
 struct ConstArgs {
   int64_t nvox;
   const int32_t* gid;

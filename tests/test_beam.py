@@ -106,10 +106,10 @@ def test_reduced_beam_cell_matches_oracle(lib, scheme):
     The bar is looser than the 1e-10 of the single-material cells: both solves stop at a
     relative CG residual of 1e-10, and with a stiffness contrast of 1e6 the projected operator's
     condition number lets two stopping points that differ only in rounding order lie up to
-    1e6 x 1e-10 apart. Measured (rotated / standard): 4e-10 / 1.1e-9 on <P> (relative to its
-    largest entry), 6e-10 / 1.6e-8 on F - I. The bar is 100 times the CG tolerance, and 10 times
-    more on the F field of the standard scheme, whose CG takes 8 times as many iterations
-    (a condition number some 60 times larger)."""
+    1e6 x 1e-10 apart. Measured (rotated / standard): 7.5e-11 / 3.8e-10 on <P> (relative to its
+    largest entry), 2.5e-10 / 1.8e-8 on F - I. The bar is 100 times the CG tolerance, and 10 times
+    more on the F field of the standard scheme, whose CG takes 5 times as many iterations
+    (a condition number some 25 times larger)."""
     rve, path, geom = synth.beam_cell(n_beam=50, n_clamp=4, n_depth=4, n_soft=4)
     freq = 0 if scheme == "rotated" else 1
     h = lib.Homogenizer([rve], precision=lib.RVE_FP64, newton_tol=1e-11, cg_tol=1e-10, max_cg=200000,

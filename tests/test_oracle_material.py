@@ -52,7 +52,8 @@ def test_converged_slip_solves_flow_rule_and_shares_root():
 
 
 def test_state_update_formulas():
-    """Fp = (I + sum dg s(x)m) Fp_n (eq. 2, backward Euler); Fe = F Fp^-1; rho_SSD by eq. 8;
+    """Fp = (I + sum dg s(x)m) Fp_n (eq. 2, backward Euler); Fe = F Fp^-1; rho_SSD by eq. 8
+    integrated over the increment with the mean free path frozen;
     tau_c by eq. 7 with the forest densities; P from S by eq. 14."""
     mat, model, gid, F, Fp_n, rs, rg = _setup()
     out = cst.update(model, gid, F, Fp_n, rs, rg, 0.5, np.zeros_like(rs))
@@ -67,8 +68,11 @@ def test_state_update_formulas():
     q = model.q
     forest = rs + mat.c_gnd * rg
     ell = mat.K_sim / np.sqrt(forest.sum(1, keepdims=True) - forest)
-    rho_new = rs + (1 / mat.burgers) * (1 / ell - 2 * mat.y_c * rs) * np.abs(out["dg"])
-    assert np.allclose(out["rho_ssd"], rho_new, rtol=1e-14)
+    # eq. 8 over the increment with l frozen: rho_n exp(-x) + u (1 - exp(-x)) / (x b l)
+    u = np.abs(out["dg"])
+    x = 2 * mat.y_c * u / mat.burgers
+    rho_new = rs * np.exp(-x) + np.where(x > 0, u * (1 - np.exp(-x)) / np.where(x > 0, x, 1), u) / (mat.burgers * ell)
+    assert np.allclose(out["rho_ssd"], rho_new, rtol=1e-12)
     mu = elasticity.slip_plane_shear_modulus(mat.C11, mat.C12, mat.C44)
     assert np.allclose(out["tau_c"], mu * mat.burgers * np.sqrt(forest @ q.T), rtol=1e-14)
 
@@ -195,6 +199,51 @@ def test_density_update_saturates_at_the_closed_form_fixed_point():
             # first-order steps: error of order y_c dgamma / b relative
             assert abs(rho / exact - 1) < 2e-3, (n, rho, exact)
     assert abs(rho / rho_sat - 1) < 1e-4
+
+
+def test_density_step_equals_fine_integration_with_frozen_mean_free_path():
+    """Over one increment the mean free path (eq. 9) is held at its start value, and eq. 8 is
+    then a linear ODE in the slip; the update must equal its fine-step numerical integration
+    (classical Runge-Kutta, 20000 steps) from small slips, where it is the forward-Euler step
+    to first order, to slips of 2 y_c |dg| / b up to 40 (aluminium: y_c / b near 200), where
+    the forward-Euler step would be negative.  A dropped factor 2, y_c on the wrong side or
+    the saturation density from the wrong forest each move the result."""
+    for name in ("Cu", "Al"):
+        mat = synth.material(name, rho0=1e11, c_gnd=0.0)
+        model = cst.MaterialModel(mat, [[1.0, 0.0, 0.0, 0.0]])
+        b, yc = mat.burgers, mat.y_c
+        rng = np.random.default_rng(3)
+        rho_n = rng.uniform(1e11, 5e13, size=(1, 12))
+        pd = cst.PointData(model, np.zeros(1, dtype=np.int64), np.eye(3)[None], rho_n, np.zeros((1, 12)))
+        inv_ell = 1.0 / pd.ell                                   # (1, 12), frozen
+        for gam in (1e-6, 1e-3, 0.1 * b / yc, 20.0 * b / yc):
+            rho = rho_n.copy()
+            steps = 20000
+            dgam = gam / steps
+            f = lambda r: (inv_ell - 2.0 * yc * r) / b
+            for _ in range(steps):
+                k1 = f(rho)
+                k2 = f(rho + 0.5 * dgam * k1)
+                k3 = f(rho + 0.5 * dgam * k2)
+                k4 = f(rho + dgam * k3)
+                rho = rho + dgam * (k1 + 2 * k2 + 2 * k3 + k4) / 6.0
+            out = cst._rho_ssd(pd, np.full((1, 12), gam))
+            assert np.allclose(out, rho, rtol=1e-10, atol=0), (name, gam)
+            assert np.all(out > 0)
+            euler = rho_n + pd.h_ssd * gam
+            if 2.0 * yc * gam / b < 1e-2:
+                assert np.allclose(out, euler, rtol=1e-2 * 2.0 * yc * gam / b + 1e-14)
+        # far past saturation the forward-Euler step turns negative; the exact step stays between
+        # the start and the saturation density 1 / (2 y_c l)
+        gam = 40.0 * b / (2.0 * yc)
+        rho_hi = np.full((1, 12), 1e15)
+        pd = cst.PointData(model, np.zeros(1, dtype=np.int64), np.eye(3)[None], rho_hi, np.zeros((1, 12)))
+        sat = 1.0 / (2.0 * yc * pd.ell)
+        out = cst._rho_ssd(pd, np.full((1, 12), gam))
+        assert np.all(rho_hi + pd.h_ssd * gam < 0)
+        lo, hi = np.minimum(rho_hi, sat), np.maximum(rho_hi, sat)
+        assert np.all((out >= lo * (1 - 1e-12)) & (out <= hi * (1 + 1e-12)))
+        assert np.allclose(out, sat, rtol=1e-12)                # exp(-40): saturated
 
 
 def test_density_fixed_point_doubles_with_an_equal_gnd_forest():
