@@ -118,6 +118,15 @@ class Homogenizer:
         check(lib().rve_get_field(self.h, i, which, _dp(out)))
         return out
 
+    def nye_gnd(self, i=0):
+        """rve_nye_gnd: the committed Nye tensor (9 x nvox, 1/m) and GND densities (12 x nvox,
+        1/m^2) of RVE i, component-major."""
+        n = self.rves[i].n_vox
+        nye = np.zeros((9, n))
+        rho = np.zeros((12, n))
+        check(lib().rve_nye_gnd(self.h, i, _dp(nye), _dp(rho)))
+        return nye, rho
+
     def timing_start(self, families=()):
         """Time the launches of the named kernel families (see _lib.KERNEL_FAMILIES) with
         HIP events from now on; an empty list stops timing.  Clears the accumulators."""

@@ -297,6 +297,7 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
   const int64_t base = (int64_t)c * nv + (int64_t)z * ny * nx;
   double acc = 0.0;
   const double beta = (MODE == PI_CG) ? a.cg->beta : 0.0;
+  const double alpha = (MODE == PI_CG) ? a.cg->alpha : 0.0;   // of the previous iteration
   const bool first = (MODE == PI_CG) ? (a.cg->iter == 0) : true;
   for (int b0 = tid; b0 < ny * nx; b0 += 4 * nthr) {
     double w[4];
@@ -328,6 +329,10 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
         const T pv = first ? r0[u] : (T)((double)r0[u] + beta * (double)p0[u]);
         reinterpret_cast<T*>(a.q)[o] = qv;
         reinterpret_cast<T*>(a.p)[o] = pv;
+        if (!first) {
+          T* X = reinterpret_cast<T*>(a.x);
+          X[o] = (T)((double)X[o] + alpha * (double)p0[u]);
+        }
         acc += (double)pv * (double)qv;
       } else if (MODE == PI_OUT_T) {
         reinterpret_cast<T*>(a.out)[o] = (T)w[u];
@@ -358,14 +363,16 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
 
 // Gradient stencil of the factorised projection and the CG epilogue (see GradArgs):
 //   q_ij = D_j w_i + dc_ij,  D_j = 1/4 (S_j - 1) prod_{m != j} (1 + S_m),
-// from the eight corners x + {0,1}^3 of each voxel (periodic), then q = q + beta q_prev,
-// p = r + beta p and the per-block p.q.  Grid: (blocks over the ny nx columns, z chunks).
+// from the eight corners x + {0,1}^3 of each voxel (periodic), then the previous iteration's
+// x += alpha p, q = q + beta q_prev, p = r + beta p and the per-block p.q.  Grid: (blocks over
+// the ny nx columns, z chunks).
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
   if (cg->done) return;
   const double beta = cg->beta;
+  const double alpha = cg->alpha;   // of the previous iteration
   const bool first = cg->iter == 0;
   const int nx = g.nx, ny = g.ny, nz = g.nz, npl = nx * ny;
   const int64_t nv = g.nvox;
@@ -373,6 +380,7 @@ __global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
   const T* Rr = reinterpret_cast<const T*>(a.r);
   T* P = reinterpret_cast<T*>(a.p);
   T* Q = reinterpret_cast<T*>(a.q);
+  T* X = reinterpret_cast<T*>(a.x);
   double dc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) dc[c] = a.dc[c];
@@ -421,6 +429,7 @@ __global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
         const T pv = first ? r0[c] : (T)((double)r0[c] + beta * (double)p0[c]);
         Q[c * nv + o] = qv;
         P[c * nv + o] = pv;
+        if (!first) X[c * nv + o] = (T)((double)X[c * nv + o] + alpha * (double)p0[c]);
         acc += (double)pv * (double)qv;
       }
 #pragma unroll
@@ -442,9 +451,11 @@ __device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
   }
 }
 
-// x += alpha p, r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame; with TR,
+// r -= alpha q (iteration > 0), partial r.r, y = K : r (sample frame; with TR,
 // y = K^T : r, (K^T)_(ij)(kl) = K_(kl)(ij), for the adjoint system); the iterate is copied to
-// xbest first when the previous iteration set a new best r.r.
+// xbest when the previous iteration set a new best r.r.  The iterate's own update x += alpha p
+// is taken by the epilogue pass of the next iteration, which reads p anyway (k_cg_finish adds
+// the last one).
 template <typename T, int K16, int TR>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
@@ -457,7 +468,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
   T* X = reinterpret_cast<T*>(a.x);
   T* XB = reinterpret_cast<T*>(a.xbest);
   T* Rr = reinterpret_cast<T*>(a.r);
-  const T* P = reinterpret_cast<const T*>(a.p);
   const T* Q = reinterpret_cast<const T*>(a.q);
   // tangent in the grouped layout: G vector loads of W entries per voxel
   using KG = TangentGroups<T>;
@@ -472,7 +482,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const int64_t o = c * nv + v;
-        X[o] = (T)((double)X[o] + alpha * (double)P[o]);
         const T rn = (T)((double)Rr[o] - alpha * (double)Q[o]);
         Rr[o] = rn;
         rs[c] = (double)rn;
@@ -732,6 +741,29 @@ void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipSt
 }
 
 int plane_blocks(const GridPlan& g) { return 9 * g.nz; }
+
+namespace {
+// The last pending iterate update of a CG solve: x += alpha p when at least one iteration ran
+// (the epilogue pass of the iteration that would have taken it returned on the stop flag, and
+// a breakdown leaves alpha = 0).
+template <typename T>
+__global__ void k_cg_finish(const CGState* cg, T* x, const T* p, int64_t n) {
+  if (cg->iter == 0) return;
+  const double alpha = cg->alpha;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)((double)x[i] + alpha * (double)p[i]);
+}
+}  // namespace
+
+void launch_cg_finish(const CGState* cg, bool fp32, void* x, const void* p, int64_t n, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>((n + 255) / 256, 2048);
+  if (fp32)
+    hipLaunchKernelGGL(k_cg_finish<float>, dim3(nb), dim3(256), 0, st, cg, static_cast<float*>(x),
+                       static_cast<const float*>(p), n);
+  else
+    hipLaunchKernelGGL(k_cg_finish<double>, dim3(nb), dim3(256), 0, st, cg, static_cast<double*>(x),
+                       static_cast<const double*>(p), n);
+}
 
 bool factorised_fits(const GridPlan& g) { return g.freq == FREQ_ROTATED && plane_ppt(g, kPlane3Threads) <= 9; }
 

@@ -503,22 +503,23 @@ struct EventTimer final : LaunchTimer {
 // output written once).  T = spectral precision, nv voxels, ns = nxh ny nz spectral points.
 static int64_t bytes_mid(const GridPlan& g, bool fp32) { return 2 * 9 * 2 * (fp32 ? 4 : 8) * g.nspec; }
 static int64_t bytes_cg_prep(const GridPlan& g, bool fp32, bool k16, bool first) {
-  // x, p, r, q, K read and x, r, y written (first iteration: r, K read and y written);
-  // K: 81 entries, or 41 pairs of FP16
+  // r, q, K read and r, y written (first iteration: r, K read and y written); K: 81 entries,
+  // or 41 pairs of FP16; grain id
   const int t = fp32 ? 4 : 8;
-  return ((first ? 18 : 63) * t + (k16 ? 41 * 4 : 81 * t) + 4) * g.nvox;
+  return ((first ? 18 : 36) * t + (k16 ? 41 * 4 : 81 * t) + 4) * g.nvox;
 }
 static int64_t bytes_plane_fwd_cg(const GridPlan& g, bool fp32) {
   const int t = fp32 ? 4 : 8;
   return 9 * t * g.nvox + 9 * 2 * t * g.nspec;  // y read, spectrum written
 }
-static int64_t bytes_plane_inv_cg(const GridPlan& g, bool fp32) {
+static int64_t bytes_plane_inv_cg(const GridPlan& g, bool fp32, bool first) {
+  // spectrum, r read; p, q, x read and written (first iteration: p, q written)
   const int t = fp32 ? 4 : 8;
-  return 9 * 2 * t * g.nspec + 45 * t * g.nvox;  // spectrum, r read; p, q read and written
+  return 9 * 2 * t * g.nspec + (first ? 27 : 63) * t * g.nvox;
 }
 // factorised projection: y read and three spectra written; three spectra read and written;
-// three spectra read and w written; w, r read, p, q read and written (first iteration: w, r
-// read, p, q written)
+// three spectra read and w written; w, r read, p, q, x read and written (first iteration: w,
+// r read, p, q written)
 static int64_t bytes_plane_div(const GridPlan& g, bool fp32) {
   const int t = fp32 ? 4 : 8;
   return 9 * t * g.nvox + 3 * 2 * t * g.nspec;
@@ -530,7 +531,7 @@ static int64_t bytes_plane_inv3(const GridPlan& g, bool fp32) {
 }
 static int64_t bytes_cg_grad(const GridPlan& g, bool fp32, bool first) {
   const int t = fp32 ? 4 : 8;
-  return (first ? 30 : 48) * t * g.nvox;
+  return (first ? 30 : 66) * t * g.nvox;
 }
 static int64_t bytes_plane_fwd_f64(const GridPlan& g, bool fp32) {
   return 9 * 8 * g.nvox + 9 * 2 * (fp32 ? 4 : 8) * g.nspec;  // FP64 field read, spectrum written
@@ -929,6 +930,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   {
     CGState s = *R.host_cg;
     s.iter = 0;
+    s.alpha = 0.0;
     s.rr_best = s.rr0;
     s.it_best = 0;
     s.done = (s.rr0 > 0.0 && C.opt.max_cg > 0) ? 0 : 1;
@@ -963,6 +965,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   std::memset(&xi, 0, sizeof(xi));
   xi.mode = XI_CG;
   xi.spec = w.spec.p;
+  xi.x = x;
   xi.r = w.r.p;
   xi.p = w.p.p;
   xi.q = w.q.p;
@@ -989,6 +992,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   std::memset(&pi, 0, sizeof(pi));
   pi.mode = PI_CG;
   pi.spec = w.spec.p;
+  pi.x = x;
   pi.r = w.r.p;
   pi.p = w.p.p;
   pi.q = w.q.p;
@@ -1020,6 +1024,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   GradArgs ga;
   std::memset(&ga, 0, sizeof(ga));
   ga.w = w.w3.p;
+  ga.x = x;
   ga.dc = part + 3584;
   ga.r = w.r.p;
   ga.p = w.p.p;
@@ -1069,7 +1074,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
         launch_mid(g, w.fp32, m, R.stream);
       }
       {
-        TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_cg(g, w.fp32), R.stream);
+        TimedLaunch t(R.tm(), KF_PLANE_INV, bytes_plane_inv_cg(g, w.fp32, issued == 0), R.stream);
         launch_plane_inv(g, w.fp32, pi, R.stream);
       }
       launch_cg_alpha(cg, part + 2048, plane_blocks(g), R.stream);
@@ -1127,6 +1132,9 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
       if (R.host_poll[(c - 1) & 1].done) break;
     }
   }
+  // the last iteration's x += alpha p (its epilogue pass returned on the stop flag)
+  launch_cg_finish(cg, w.fp32, x, w.p.p, 9 * g.nvox, R.stream);
+  check_launch("cg finish");
   HIPCHECK(hipMemcpyAsync(R.host_cg, cg, sizeof(CGState), hipMemcpyDeviceToHost, R.stream));
   HIPCHECK(hipStreamSynchronize(R.stream));
   R.timer.resolve(R.host_cg->iter);
@@ -1891,10 +1899,13 @@ int32_t rve_get_field(rve_handle h, int32_t rve, int32_t which, double* out) {
 }
 
 int32_t rve_nye_gnd(rve_handle h, int32_t rve, double* nye, double* rho_gnd) {
-  int32_t rc = RVE_OK;
-  if (nye) rc = rve_get_field(h, rve, 5, nye);
-  if (rc == RVE_OK && rho_gnd) rc = rve_get_field(h, rve, 4, rho_gnd);
-  return rc;
+  return guarded([&]() -> int32_t {
+    if (!h || rve < 0 || rve >= (int32_t)h->rves.size()) throw Error(RVE_EINVAL, "bad rve index");
+    int32_t rc = RVE_OK;
+    if (nye) rc = rve_get_field(h, rve, 5, nye);
+    if (rc == RVE_OK && rho_gnd) rc = rve_get_field(h, rve, 4, rho_gnd);
+    return rc;
+  });
 }
 
 int32_t rve_adjoint_solve(rve_handle h, int32_t rve, const uint8_t* mask, const double* g, double* lambda,

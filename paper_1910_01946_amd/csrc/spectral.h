@@ -37,10 +37,12 @@ enum FreqScheme { FREQ_ROTATED = 0, FREQ_STANDARD = 1 };
 //
 // The operator is applied to the residual and the search-direction image follows by
 // linearity, so that every dot product is taken from stored vectors:
-//   forward x pass (iteration k > 0):  x += alpha p,  r -= alpha q;  partial r.r;  K : r
+//   forward x pass (iteration k > 0):  r -= alpha q;  partial r.r;  K : r
 //   beta kernel:   beta = r.r / (previous r.r);  stop if r.r <= tol2 r0.r0
-//   inverse x pass: w = G(K : r);  q = w + beta q,  p = r + beta p;  partial p.q
+//   inverse x pass: w = G(K : r);  x += alpha p (iteration k > 0, the previous p and alpha),
+//                  q = w + beta q,  p = r + beta p;  partial p.q
 //   alpha kernel:  alpha = r.r / p.q
+// and after the last iteration k_cg_finish adds the pending alpha p to x.
 // (q = G(K : p) by linearity of the projected operator).  Taking p.q from the projected
 // q keeps alpha consistent with the operator actually applied (p.Kp equals p.G(Kp) only
 // while p lies exactly in the range of G, which FP32 rounding does not preserve), and
@@ -223,6 +225,7 @@ struct PlaneInvArgs {
 // column and carries the corner values of the upper plane to the next step.
 struct GradArgs {
   const void* w;               // 3 x nvox (T)
+  void* x;                     // the CG iterate: x += alpha p of the previous iteration
   const double* dc;            // 9 values
   const void* r;
   void* p;
@@ -262,6 +265,8 @@ bool factorised_fits(const GridPlan& g);
 int grad_blocks(const GridPlan& g, int lz);
 int grad_lz(const GridPlan& g);
 void launch_cg_grad(const GridPlan& g, bool fp32, const GradArgs& a, hipStream_t st);
+// x += alpha p for the last iteration of a CG solve (n = 9 nvox values of the CG precision)
+void launch_cg_finish(const CGState* cg, bool fp32, void* x, const void* p, int64_t n, hipStream_t st);
 void launch_plane_fwd(const GridPlan& g, bool fp32, const PlaneArgs& a, CGState* cg, hipStream_t st);
 void launch_plane_inv(const GridPlan& g, bool fp32, const PlaneInvArgs& a, hipStream_t st);
 // k16: the tangent copy is FP16 pairs scaled by 1/k_scale (grouped layout of

@@ -68,7 +68,6 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
       } else {
         T* X = reinterpret_cast<T*>(a.x);
         T* r = reinterpret_cast<T*>(a.r);
-        const T* p = reinterpret_cast<const T*>(a.p);
         const T* q = reinterpret_cast<const T*>(a.q);
         const T* K = reinterpret_cast<const T*>(a.K);
         double ps[9];
@@ -82,7 +81,6 @@ __global__ void k_xfwd(GridPlan g, XFwdArgs a) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const int64_t o = c * nv + v;
-            X[o] = (T)((double)X[o] + alpha * (double)p[o]);
             const T rn = (T)((double)r[o] - alpha * (double)q[o]);
             r[o] = rn;
             ps[c] = (double)rn;
@@ -374,12 +372,15 @@ __global__ void k_xinv(GridPlan g, XInvArgs a) {
         const T* R = reinterpret_cast<const T*>(a.r);
         T* P = reinterpret_cast<T*>(a.p);
         if (a.cg->iter > 0) {
-          const double beta = a.cg->beta;
+          const double beta = a.cg->beta, alpha = a.cg->alpha;
+          T* X = reinterpret_cast<T*>(a.x);
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const int64_t o = c * nv + v;
+            const T pold = P[o];
             const T qv = (T)(q[c] + beta * (double)Q[o]);
-            const T pv = (T)((double)R[o] + beta * (double)P[o]);
+            const T pv = (T)((double)R[o] + beta * (double)pold);
+            X[o] = (T)((double)X[o] + alpha * (double)pold);
             Q[o] = qv;
             P[o] = pv;
             acc += (double)pv * (double)qv;

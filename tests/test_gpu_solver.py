@@ -359,6 +359,25 @@ def test_batch_of_uneven_rves_equals_separate_handles(lib):
     assert np.array_equal(hb.field("rho_gnd", 1), hs.field("rho_gnd", 0))
 
 
+def test_nye_gnd_returns_the_committed_fields(lib):
+    """rve_nye_gnd hands out the Nye tensor and GND densities that the last increment committed
+    (the same values as the field reader), for each RVE of a batch."""
+    mat = synth.material("Cu", rho0=1e11, c_gnd=1.0)
+    rves = [synth.voronoi_rve(700 + i, (8, 8, 8), 4, 2e-6, mat) for i in range(2)]
+    path = synth.uniaxial_tension(0.05, 50, 1e-4)
+    h = lib.Homogenizer(rves, precision=lib.RVE_FP64, newton_tol=1e-10, cg_tol=1e-8)
+    for k in (1, 2):
+        h.step(path.F_bar[k], path.mask, path.P_bar[k], path.dt)
+    for i in range(2):
+        nye, rho = h.nye_gnd(i)
+        assert np.array_equal(nye, h.field("nye", i))
+        assert np.array_equal(rho, h.field("rho_gnd", i))
+        assert np.abs(nye).max() > 0 and rho.max() > 0
+    with pytest.raises(lib.RVEError):
+        lib.check(lib.lib().rve_nye_gnd(h.h, 2, None, None))
+    h.close()
+
+
 def test_mixed_batch_with_graphs_on_concurrent_workers(lib):
     """Sixteen mixed-form RVEs on eight host workers with CG graphs: every RVE's first increment
     (when each worker captures its graphs while others start their solves) and the next one
