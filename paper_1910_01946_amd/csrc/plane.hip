@@ -768,11 +768,11 @@ void launch_cg_finish(const CGState* cg, bool fp32, void* x, const void* p, int6
 bool factorised_fits(const GridPlan& g) { return g.freq == FREQ_ROTATED && plane_ppt(g, kPlane3Threads) <= 9; }
 
 // Columns of 256 threads over the plane, z chunks of lz planes: the smallest lz that keeps
-// the grid (and the p.q partials) at 1024 blocks.
+// the grid (and the p.q partials) at kGradBlocks blocks.
 int grad_lz(const GridPlan& g) {
   const int bx = (g.nx * g.ny + 255) / 256;
   int lz = 1;
-  while ((int64_t)bx * ((g.nz + lz - 1) / lz) > 1024) ++lz;
+  while ((int64_t)bx * ((g.nz + lz - 1) / lz) > kGradBlocks) ++lz;
   return lz;
 }
 

@@ -999,8 +999,9 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   pi.cg = cg;
   pi.partial = part + 2048;
   // factorised projection (w.g3): partials of the stages in disjoint ranges of part:
-  // [0, 1024) r.r of the prep, [2048, 3072) p.q of the gradient pass, [3584, 3593) the
-  // zero-frequency term, [4096, 4096 + 9 nz) plane sums of y
+  // [0, 1024) r.r of the prep, [3584, 3593) the zero-frequency term, [4096, 4096 + 9 nz)
+  // plane sums of y, [16384, 16384 + kGradBlocks) p.q of the gradient pass (part holds at
+  // least 12 x 2048 values)
   PlaneArgs pd{PF_DIV, w.y.p, w.spec.p};
   pd.rr_partial = part;
   pd.n_rr = prep_blocks(g);
@@ -1030,7 +1031,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
   ga.p = w.p.p;
   ga.q = w.q.p;
   ga.cg = cg;
-  ga.partial = part + 2048;
+  ga.partial = part + 16384;
   ga.lz = grad_lz(g);
   const int chunk = 4;
   int issued = 0;  // CG iterations launched so far
@@ -1062,7 +1063,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
           TimedLaunch t(R.tm(), KF_CG_GRAD, bytes_cg_grad(g, w.fp32, issued == 0), R.stream);
           launch_cg_grad(g, w.fp32, ga, R.stream);
         }
-        launch_cg_alpha(cg, part + 2048, grad_blocks(g, ga.lz), R.stream);
+        launch_cg_alpha(cg, part + 16384, grad_blocks(g, ga.lz), R.stream);
         continue;
       }
       {

@@ -262,6 +262,8 @@ int prep_blocks(const GridPlan& g);
 // plane kernels (planes to about 128 x 128, all that the plane path holds in LDS); the caller
 // checks plane_fits for its precision.
 bool factorised_fits(const GridPlan& g);
+// most blocks (and p.q partials) of the gradient pass
+constexpr int kGradBlocks = 4096;
 int grad_blocks(const GridPlan& g, int lz);
 int grad_lz(const GridPlan& g);
 void launch_cg_grad(const GridPlan& g, bool fp32, const GradArgs& a, hipStream_t st);
