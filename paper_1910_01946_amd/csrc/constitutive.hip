@@ -18,15 +18,16 @@
 // Local solve.  Newton on R(dg) = 0 with the analytic Jacobian
 //   J_ab = delta_ab + D_a (u_b . Chat_a w_b),  D_a = d g_a / d tau_a,
 //   u_b = Ce s_b, w_b = A^{-T} m_b, Chat_a = C : sym(s_a (x) m_a),
-// solved by Gaussian elimination without pivoting (J = D (D^{-1} + M) with M close to a
-// symmetric positive semi-definite Gram matrix, so elimination is stable), steps capped
-// at 0.02 in the max norm and backtracked on |R|.  If 25 Newton steps at the final
+// whose non-identity part has rank at most six: each solve with J runs as a 6x6
+// elimination on symmetric tensors (rank6_build below); steps are capped at 0.02 in the
+// max norm and backtracked on |R|.  If 12 Newton steps at the final
 // exponent do not converge from the warm start, the lane restarts with continuation in
 // the exponent (roots at n = 1, 2, 4, 8, 16, then n = 1/m): far from the solution the
 // Jacobian rows of overloaded systems carry (|tau|/tau_c)^(n-1) and J becomes
 // numerically singular; each continuation stage starts close to its own root.
 //
-// Tangent.  With the converged J (plain rows), for each unit direction dF = e_k (x) e_l:
+// Tangent.  With the converged J (through the same 6x6 form), for each unit direction
+// dF = e_k (x) e_l:
 //   dtau_a = Fe_k. Chat_a G_l.  (G = Fp^{-1}),  ddg = J^{-1} (D dtau),  Z = sum_b ddg_b s_b (x) m_b,
 //   dEe = sym(Fe_k. (x) G_l.) - sym(Ce Z A^{-1}),  dS = C : dEe,
 //   dP = e_k (x) (G S G^T)_l. - Fe Z A^{-1} S G^T + Fe dS G^T - Fe S A^{-T} Z^T G^T.
@@ -177,19 +178,119 @@ __device__ __forceinline__ void lu12_solve(const double J[12][12], double* x) {
   }
 }
 
+// Rank-six form of the same Jacobian.  With P_a = sym(s_a (x) m_a) and Chat_a = C : P_a,
+//   J = I + D H^T W,   (H^T X)_a = Chat_a : X,   W x = sum_b x_b sym(u_b (x) w_b),
+// so J has the identity plus a part of rank at most six (symmetric tensors), and the
+// Sherman-Morrison-Woodbury identity turns every solve with J into one with the 6x6 operator
+//   N = C^{-1} + G,   G T = sum_a D_a sym(u_a (x) w_a) (P_a : T):
+//   J d = -R   <=>   N T = W R,  d_a = -R_a + D_a P_a : T
+//   J x = D H^T E (E symmetric)   <=>   N T = E,  x_a = D_a P_a : T.
+// Symmetric tensors are held as (11, 22, 33, 23, 13, 12) components; with the weights
+// omega = (1, 1, 1, 2, 2, 2) of the double contraction, the rows of N are scaled by omega,
+// which makes the stored matrix symmetric where sym(u_a (x) w_a) = P_a (Ce = A = I) and
+// positive definite there (compliance plus a Gram matrix with D >= 0), so it is eliminated
+// without pivoting like the 12x12 form.
+__device__ constexpr int kVi[6] = {0, 1, 2, 1, 0, 0};
+__device__ constexpr int kVj[6] = {0, 1, 2, 2, 2, 1};
+
+// omega-weighted component l of P_a
+__device__ __forceinline__ double pw(int a, int l) {
+  const int i = kVi[l], j = kVj[l];
+  return (l < 3) ? kSlipS[a][i] * kSlipM[a][i] : kSlipS[a][i] * kSlipM[a][j] + kSlipS[a][j] * kSlipM[a][i];
+}
+
+// N (row-scaled by omega) and, when R is given, y = omega * (W R).
+__device__ __forceinline__ void rank6_build(const Point& p, const Kin& k, const double* D, const double* R,
+                                            double N[6][6], double* y) {
+  const double det = (p.C11 - p.C12) * (p.C11 + 2.0 * p.C12);
+  const double s11 = (p.C11 + p.C12) / det, s12 = -p.C12 / det, s44 = 1.0 / p.C44;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    if (R) y[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      N[r][c] = (r < 3 && c < 3) ? ((r == c) ? s11 : s12) : ((r == c) ? s44 : 0.0);
+  }
+#pragma unroll
+  for (int b = 0; b < 12; ++b) {
+    double u[3], w[3], wv[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[i] = k.Ce[3 * i] * kSlipS[b][0] + k.Ce[3 * i + 1] * kSlipS[b][1] + k.Ce[3 * i + 2] * kSlipS[b][2];
+      w[i] = k.Ainv[i] * kSlipM[b][0] + k.Ainv[3 + i] * kSlipM[b][1] + k.Ainv[6 + i] * kSlipM[b][2];
+    }
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+      wv[l] = (l < 3) ? u[kVi[l]] * w[kVi[l]] : u[kVi[l]] * w[kVj[l]] + u[kVj[l]] * w[kVi[l]];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      if (R) y[r] += R[b] * wv[r];
+      const double dw = D[b] * wv[r];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) N[r][c] += dw * pw(b, c);
+    }
+  }
+}
+
+__device__ __forceinline__ void lu6(double N[6][6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double ip = 1.0 / N[c][c];
+#pragma unroll
+    for (int r = c + 1; r < 6; ++r) {
+      const double f = N[r][c] * ip;
+      N[r][c] = f;
+#pragma unroll
+      for (int cc = c + 1; cc < 6; ++cc) N[r][cc] -= f * N[c][cc];
+    }
+  }
+}
+
+__device__ __forceinline__ void lu6_solve(const double N[6][6], double* x) {
+#pragma unroll
+  for (int r = 1; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < r; ++c) x[r] -= N[r][c] * x[c];
+#pragma unroll
+  for (int r = 5; r >= 0; --r) {
+#pragma unroll
+    for (int c = r + 1; c < 6; ++c) x[r] -= N[r][c] * x[c];
+    x[r] /= N[r][r];
+  }
+}
+
+// x_a = D_a P_a : T
+__device__ __forceinline__ void rank6_expand(const double* D, const double* T, double* x) {
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) s += pw(a, l) * T[l];
+    x[a] = D[a] * s;
+  }
+}
+
+// Newton direction d = -J^{-1} R through the 6x6 form.
+__device__ __forceinline__ void newton_direction(const Point& p, const Kin& k, const double* D, const double* R,
+                                                 double* d) {
+  double N[6][6], T[6];
+  rank6_build(p, k, D, R, N, T);
+  lu6(N);
+  lu6_solve(N, T);
+  rank6_expand(D, T, d);
+#pragma unroll
+  for (int a = 0; a < 12; ++a) d[a] -= R[a];
+}
+
 // Newton iterations at exponent n; returns 1 if converged.  iters accumulates.  The line
 // search works in place: a rejected trial dg + lam d is pulled back by lam/2 d.
 __device__ int newton(const Point& p, double n, double tol, int maxit, double* dg, int& iters) {
   const double floor_ = 1e-10, max_step = 0.02;
   Kin k;
-  double R[12], D[12], J[12][12], d[12];
+  double R[12], D[12], d[12];
   for (int it = 0; it < maxit; ++it) {
     const double r2 = residual(p, n, dg, k, R, D);
-    jacobian(p, k, D, J);
-    lu12(J);
-#pragma unroll
-    for (int a = 0; a < 12; ++a) d[a] = -R[a];
-    lu12_solve(J, d);
+    newton_direction(p, k, D, R, d);
     ++iters;
     // fmax drops NaN operands, so finiteness is tested per component (a NaN compares false)
     double big = 0.0, xmax = 0.0;
@@ -343,12 +444,12 @@ __global__ void __launch_bounds__(64) k_slip_slow(ConstArgs args) {
 #pragma unroll
     for (int a = 0; a < 12; ++a) dg[a] = args.dg[a * nv + v];
     const double n_final = M.n_exp;
-    const double stages[5] = {1.0, 2.0, 4.0, 8.0, 16.0};
     int it = kFastIters, ok = 0;
+#pragma unroll 1
     for (int pass = 0; pass < 6; ++pass) {
       double n = n_final, tol = 1e-10;
       if (pass < 5) {
-        n = stages[pass];
+        n = (double)(1 << pass);   // 1, 2, 4, 8, 16
         tol = 1e-4;
         if (n >= n_final) continue;
       }
@@ -393,9 +494,9 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) args.P[i * nv + v] = Ps[i];
   if (!args.K) return;
-  double J[12][12];
-  jacobian(p, k, D, J);
-  lu12(J);
+  double N[6][6];
+  rank6_build(p, k, D, nullptr, N, nullptr);
+  lu6(N);
   double H[9], Q[9], W[9], AtS[9];
   mm3(G, SGt, H);                  // G S G^T
   mm3(k.Ainv, SGt, Q);             // A^{-1} S G^T
@@ -406,12 +507,22 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
   for (int kk = 0; kk < 3; ++kk) {
 #pragma unroll 1
     for (int ll = 0; ll < 3; ++ll) {
-      const double av[3] = {k.Fe[3 * kk], k.Fe[3 * kk + 1], k.Fe[3 * kk + 2]};
-      const double bv[3] = {G[3 * ll], G[3 * ll + 1], G[3 * ll + 2]};
-      double x[12];
+      // rows kk of Fe and ll of G by selection: a loop-variable index into a register array
+      // would place the array in scratch memory
+      double av[3], bv[3], hv[3];
 #pragma unroll
-      for (int a = 0; a < 12; ++a) x[a] = D[a] * uCw(p, a, av, bv);
-      lu12_solve(J, x);
+      for (int i = 0; i < 3; ++i) {
+        av[i] = kk == 0 ? k.Fe[i] : (kk == 1 ? k.Fe[3 + i] : k.Fe[6 + i]);
+        bv[i] = ll == 0 ? G[i] : (ll == 1 ? G[3 + i] : G[6 + i]);
+        hv[i] = ll == 0 ? H[i] : (ll == 1 ? H[3 + i] : H[6 + i]);
+      }
+      // ddg = J^{-1} D H^T sym(av (x) bv), through the 6x6 form
+      double T[6], x[12];
+#pragma unroll
+      for (int l = 0; l < 6; ++l)
+        T[l] = (l < 3) ? av[kVi[l]] * bv[kVi[l]] : av[kVi[l]] * bv[kVj[l]] + av[kVj[l]] * bv[kVi[l]];
+      lu6_solve(N, T);
+      rank6_expand(D, T, x);
       if (args.dgdF) {
 #pragma unroll
         for (int a = 0; a < 12; ++a) args.dgdF[(int64_t)(9 * a + 3 * kk + ll) * nv + v] = (float)x[a];
@@ -449,7 +560,8 @@ __global__ void __launch_bounds__(64) k_stress_tangent(ConstArgs args) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) dP[i] -= t2[i];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) dP[3 * kk + j] += H[3 * ll + j];   // + e_k (x) H_l.
+      for (int r = 0; r < 9; ++r)
+        if (r / 3 == kk) dP[r] += hv[r % 3];                   // + e_k (x) H_l.
       const int col = 3 * kk + ll;
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
