@@ -937,6 +937,7 @@ static int run_cg(Ctx& C, RVE& R, Work& w, void* x, const double* mask_keep, int
     s.tol2 = C.opt.cg_tol * C.opt.cg_tol;
     s.rr_floor = rr_floor;
     s.max_iter = C.opt.max_cg;
+    s.stall = w.fp32 ? kCgStall : kCgStall64;
     *R.host_cg = s;
     HIPCHECK(hipMemcpyAsync(cg, R.host_cg, sizeof(CGState), hipMemcpyHostToDevice, R.stream));
   }

@@ -58,15 +58,23 @@ struct CGState {
                    // (FP32 spectra), below which no correction is resolved
   int32_t iter;    // completed operator applications
   int32_t done;    // 0 running, 1 converged, 2 breakdown (p.q <= 0), 3 diverging (r.r > 1e4 r0.r0),
-                   // 4 max_iter, 5 stalled (|r| not halved within kCgStall iterations)
+                   // 4 max_iter, 5 stalled (|r| not halved within `stall` iterations)
   int32_t max_iter;
   int32_t it_best; // iteration of rr_best
+  int32_t stall;   // stalled (5) once |r| has not halved for this many iterations
+  int32_t pad;
 };
 
-// A solve whose residual norm has not halved for this many iterations has reached the
+// A solve whose residual norm has not halved for kCgStall iterations has reached the
 // rounding floor of the operator (the consistent tangent is not symmetric, and CG on a
 // right-hand side at that floor need not converge): it stops with its current iterate.
+// FP64 solves wait longer: on a badly conditioned operator (a stiffness contrast of 1e6
+// with the standard frequencies) the residual norm of CG can plateau for over a thousand
+// iterations far above its rounding floor before it falls again, and a stop there hands
+// Newton a correction that has not resolved the residual.  The FP32 form's floor also
+// ends the solve through rr_floor.
 constexpr int kCgStall = 500;
+constexpr int kCgStall64 = 2000;
 
 enum XFwdMode { XF_FIELD64 = 0, XF_CG = 1, XF_FP_MINUS_I = 2 };
 enum XInvMode { XI_RESID = 0, XI_CG = 1, XI_NYE = 2, XI_OUT64 = 3 };
@@ -135,7 +143,7 @@ __device__ inline void cg_beta_update(CGState* cg, double rr, bool first) {
   if (rr <= cg->tol2 * cg->rr0 || rr <= cg->rr_floor) cg->done = 1;
   else if (!(rr < 1e4 * cg->rr0)) cg->done = 3;
   else if (cg->iter >= cg->max_iter) cg->done = 4;
-  else if (cg->iter - cg->it_best >= kCgStall) cg->done = 5;
+  else if (cg->iter - cg->it_best >= cg->stall) cg->done = 5;
 }
 
 // alpha step, after p.q: alpha = r.r / p.q; a non-positive (or non-finite) p.q is a

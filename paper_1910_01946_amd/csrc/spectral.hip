@@ -458,6 +458,7 @@ __global__ void k_cg_start(CGState* cg, const double* partial, int n, double tol
     cg->rr_floor = 0.0;
     cg->it_best = 0;
     cg->max_iter = max_iter;
+    cg->stall = kCgStall;
     cg->alpha = 0.0;
     cg->beta = 0.0;
     cg->done = (rr > 0.0 && max_iter > 0) ? 0 : 1;
