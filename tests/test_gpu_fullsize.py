@@ -105,8 +105,12 @@ def test_converged_field_is_compatible_and_balanced(run):
         rms_P = float(np.sqrt(np.mean(P * P)))
         print("residual rms", rms_r, "stress rms", rms_P, "reported", st["res_norm"], flush=True)
         # the residual the GPU reports (FP32 spectral path) is the oracle's FP64 projection of
-        # the GPU's stress, and at a correction tolerance of 1e-6 it is a small part of the stress
-        assert abs(rms_r - st["res_norm"]) <= 1e-5 * rms_r
+        # the GPU's stress, and at a correction tolerance of 1e-6 it is a small part of the stress.
+        # The FP32 projection adds rounding noise e of rms about u32 rms(P), uncorrelated with the
+        # residual, which moves its rms by about rms(e)^2 / (2 rms_r): near that floor this term,
+        # not the relative 1e-5, bounds the difference (four times the noise estimate)
+        u32 = 2.0 ** -24
+        assert abs(rms_r - st["res_norm"]) <= 1e-5 * rms_r + (4 * u32 * rms_P) ** 2 / (2 * rms_r)
         assert rms_r < 2e-3 * rms_P
         P_avg = macro[0]
         assert abs(P_avg[4]) < 1e-4 * abs(P_avg[0]) and abs(P_avg[8]) < 1e-4 * abs(P_avg[0])
