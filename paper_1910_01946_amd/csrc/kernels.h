@@ -67,19 +67,24 @@ struct ConstArgs {
 enum TangentType : int { KT_F64 = 0, KT_F32 = 1, KT_F16 = 2 };
 
 // Layout of the tangent copy used by the conjugate-gradient kernels.  FP64 and FP16: the
-// 81 entries of a voxel in groups of W = 2 consecutive entries (16 and 4 bytes), group-major
-// over voxels, so that one lane reads two entries with one vector load while a wavefront
-// still reads contiguous memory (fewer memory instructions in flight per voxel).  FP32:
-// entry-major (W = 1); wider groups there cost more registers and occupancy than they gain.
+// 81 entries of a voxel in groups of W consecutive entries, group-major over voxels, so that
+// one lane reads W entries with one vector load while a wavefront still reads contiguous
+// memory (fewer memory instructions in flight per voxel).  FP64: W = 2 (16-byte loads, the
+// last group padded); FP16: W = 8 (16-byte loads) over entries 0-79, then entry 80 alone
+// (2 bytes per voxel, no padding); FP32: entry-major (W = 1); wider groups there cost more
+// registers and occupancy than they gain.
 template <typename KT>
 struct TangentGroups {
-  static constexpr int W = sizeof(KT) == 4 ? 1 : 2;
-  static constexpr int G = (81 + W - 1) / W;  // groups per voxel (last one padded)
+  static constexpr int W = sizeof(KT) == 4 ? 1 : (sizeof(KT) == 2 ? 8 : 2);
+  static constexpr int G = (81 + W - 1) / W;                          // groups per voxel
+  static constexpr int kStored = sizeof(KT) == 2 ? 81 : G * W;       // entries stored per voxel
 };
 template <typename KT>
 __host__ __device__ __forceinline__ int64_t tangent_index(int e, int64_t v, int64_t nv, bool grouped) {
   constexpr int W = TangentGroups<KT>::W;
-  return grouped ? ((int64_t)(e / W) * nv + v) * W + (e % W) : (int64_t)e * nv + v;
+  if (!grouped) return (int64_t)e * nv + v;
+  if (sizeof(KT) == 2 && e >= 80) return 80 * nv + v;                // FP16 tail entry
+  return ((int64_t)(e / W) * nv + v) * W + (e % W);
 }
 
 struct CommitArgs {

@@ -457,7 +457,7 @@ __device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
 // is taken by the epilogue pass of the next iteration, which reads p anyway (k_cg_finish adds
 // the last one).
 template <typename T, int K16, int TR>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
+__global__ void __launch_bounds__(256, (sizeof(T) == 4) ? (K16 ? 5 : 6) : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
   if (cg->done) return;
@@ -498,21 +498,31 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_pr
     for (int i = 0; i < 9; ++i) Rg[i] = a.grainR[9 * gi + i];
     to_crystal(Rg, rs, rc);
     if constexpr (K16 != 0) {
-      // FP16 pairs (41 4-byte loads per voxel), scaled: the tangent stream dominates the
-      // kernel's bytes, and this halves it
-      const __half2* K2 = reinterpret_cast<const __half2*>(a.K);
-      float kv[82];
+      // FP16, scaled: the tangent stream dominates the kernel's bytes, and this halves it.
+      // Entries 0-79 in ten 16-byte loads of eight, entry 80 in a 2-byte load
+      const uint4* K8 = reinterpret_cast<const uint4*>(a.K);
+      const __half* Kt = reinterpret_cast<const __half*>(a.K) + 80 * nv;
+      // (the packed words stay packed until their product: 41 registers instead of 81)
+      unsigned kw[41];
 #pragma unroll
-      for (int gq = 0; gq < 41; ++gq) {
-        const float2 f = __half22float2(K2[(int64_t)gq * nv + v]);
-        kv[2 * gq] = f.x;
-        kv[2 * gq + 1] = f.y;
+      for (int gq = 0; gq < 10; ++gq) {
+        const uint4 u = K8[(int64_t)gq * nv + v];
+        kw[4 * gq] = u.x;
+        kw[4 * gq + 1] = u.y;
+        kw[4 * gq + 2] = u.z;
+        kw[4 * gq + 3] = u.w;
       }
+      kw[40] = (unsigned)__half_as_ushort(Kt[v]);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) s += (double)kv[TR ? j * 9 + i : i * 9 + j] * rc[j];
+        for (int j = 0; j < 9; ++j) {
+          const int e = TR ? j * 9 + i : i * 9 + j;
+          const __half2 h2 = *reinterpret_cast<const __half2*>(&kw[e >> 1]);
+          const float kf = (e & 1) ? __high2float(h2) : __low2float(h2);
+          s += (double)kf * rc[j];
+        }
         yc[i] = s * a.k_scale;
       }
     } else if constexpr (KG::W == 1) {

@@ -506,7 +506,7 @@ static int64_t bytes_cg_prep(const GridPlan& g, bool fp32, bool k16, bool first)
   // r, q, K read and r, y written (first iteration: r, K read and y written); K: 81 entries,
   // or 41 pairs of FP16; grain id
   const int t = fp32 ? 4 : 8;
-  return ((first ? 18 : 36) * t + (k16 ? 41 * 4 : 81 * t) + 4) * g.nvox;
+  return ((first ? 18 : 36) * t + (k16 ? 81 * 2 : 81 * t) + 4) * g.nvox;
 }
 static int64_t bytes_plane_fwd_cg(const GridPlan& g, bool fp32) {
   const int t = fp32 ? 4 : 8;
@@ -617,8 +617,8 @@ static Work& work(RVE& R, bool fp32) {
     const int64_t nv = R.nvox;
     const size_t ts = tsize(fp32);
     // grouped layout: G groups of W entries per voxel (see tangent_index)
-    w.K.alloc(ts * (fp32 ? TangentGroups<float>::G * TangentGroups<float>::W
-                         : TangentGroups<double>::G * TangentGroups<double>::W) * nv);
+    // (an FP32 work set also holds the FP16 copy, TangentGroups<__half>::kStored <= 81 floats)
+    w.K.alloc(ts * (fp32 ? TangentGroups<float>::kStored : TangentGroups<double>::kStored) * nv);
     w.xa.alloc(ts * 9 * nv);
     w.xb.alloc(ts * 9 * nv);
     w.xbest.alloc(ts * 9 * nv);
