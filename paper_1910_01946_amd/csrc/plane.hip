@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
   const bool first = (MODE == PI_CG) ? (a.cg->iter == 0) : true;
   for (int b0 = tid; b0 < ny * nx; b0 += 4 * nthr) {
     double w[4];
-    T q0[4], p0[4], r0[4];
+    T q0[4], p0[4], r0[4], x0[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = b0 + u * nthr;
@@ -310,11 +310,13 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
         const cplx<T> e = A[(y >> 1) * SA + padded(x)];
         w[u] = (double)((y & 1) ? e.y : e.x);
         if (MODE == PI_CG) {
+          // every load (x too) before the first store, which the compiler cannot move loads past
           const int64_t o = base + idx;
           r0[u] = reinterpret_cast<const T*>(a.r)[o];
           if (!first) {
             q0[u] = reinterpret_cast<const T*>(a.q)[o];
             p0[u] = reinterpret_cast<const T*>(a.p)[o];
+            x0[u] = reinterpret_cast<const T*>(a.x)[o];
           }
         }
       }
@@ -329,10 +331,7 @@ __global__ void __launch_bounds__(plane_threads<MODE == PI_OUT_T>()) k_plane_inv
         const T pv = first ? r0[u] : (T)((double)r0[u] + beta * (double)p0[u]);
         reinterpret_cast<T*>(a.q)[o] = qv;
         reinterpret_cast<T*>(a.p)[o] = pv;
-        if (!first) {
-          T* X = reinterpret_cast<T*>(a.x);
-          X[o] = (T)((double)X[o] + alpha * (double)p0[u]);
-        }
+        if (!first) reinterpret_cast<T*>(a.x)[o] = (T)((double)x0[u] + alpha * (double)p0[u]);
         acc += (double)pv * (double)qv;
       } else if (MODE == PI_OUT_T) {
         reinterpret_cast<T*>(a.out)[o] = (T)w[u];
@@ -413,13 +412,15 @@ __global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
         qn[3 * i + 2] = 0.25 * ((hi[i][0] - lo[i][0]) + (hi[i][1] - lo[i][1]) + (hi[i][2] - lo[i][2]) +
                                 (hi[i][3] - lo[i][3]));
       }
-      T r0[9], q0[9], p0[9];
+      // every load of the voxel is issued before the first store (x too)
+      T r0[9], q0[9], p0[9], x0[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         r0[c] = Rr[c * nv + o];
         if (!first) {
           q0[c] = Q[c * nv + o];
           p0[c] = P[c * nv + o];
+          x0[c] = X[c * nv + o];
         }
       }
 #pragma unroll
@@ -429,7 +430,7 @@ __global__ void __launch_bounds__(256) k_cg_grad(GridPlan g, GradArgs a) {
         const T pv = first ? r0[c] : (T)((double)r0[c] + beta * (double)p0[c]);
         Q[c * nv + o] = qv;
         P[c * nv + o] = pv;
-        if (!first) X[c * nv + o] = (T)((double)X[c * nv + o] + alpha * (double)p0[c]);
+        if (!first) X[c * nv + o] = (T)((double)x0[c] + alpha * (double)p0[c]);
         acc += (double)pv * (double)qv;
       }
 #pragma unroll
@@ -457,7 +458,7 @@ __device__ __forceinline__ void copy_iterate(const T* X, T* XB, int64_t nv) {
 // is taken by the epilogue pass of the next iteration, which reads p anyway (k_cg_finish adds
 // the last one).
 template <typename T, int K16, int TR>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4) ? (K16 ? 5 : 6) : 4) k_cg_prep(int64_t nv, PrepArgs a) {
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && !K16) ? 6 : 4) k_cg_prep(int64_t nv, PrepArgs a) {
   __shared__ double red[8];
   const CGState* cg = a.cg;
   if (cg->done) return;
@@ -477,8 +478,43 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4) ? (K16 ? 5 : 6) : 4) k_c
   double acc = 0.0;
   if (keep) copy_iterate(X, XB, nv);
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    // Every load of the voxel is issued before its first store: a store between loads keeps
+    // the compiler (which cannot rule out aliasing) from moving the later loads ahead of it.
+    // FP16 tangent, scaled: the tangent stream dominates the kernel's bytes, and this halves
+    // it.  Entries 0-79 in ten 16-byte loads of eight, entry 80 in a 2-byte load; the packed
+    // words stay packed until their product (41 registers instead of 81).
+    unsigned kw[41];
+    if constexpr (K16 != 0) {
+      const uint4* K8 = reinterpret_cast<const uint4*>(a.K);
+      const __half* Kt = reinterpret_cast<const __half*>(a.K) + 80 * nv;
+#pragma unroll
+      for (int gq = 0; gq < 10; ++gq) {
+        const uint4 u = K8[(int64_t)gq * nv + v];
+        kw[4 * gq] = u.x;
+        kw[4 * gq + 1] = u.y;
+        kw[4 * gq + 2] = u.z;
+        kw[4 * gq + 3] = u.w;
+      }
+      kw[40] = (unsigned)__half_as_ushort(Kt[v]);
+    }
+    int gi = 0;
+    if constexpr (sizeof(T) == 4) gi = a.gid[v];
     double rs[9];
-    if (upd) {
+    if (upd && sizeof(T) == 4) {
+      T r0[9], q0[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        r0[c] = Rr[c * nv + v];
+        q0[c] = Q[c * nv + v];
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const T rn = (T)((double)r0[c] - alpha * (double)q0[c]);
+        Rr[c * nv + v] = rn;
+        rs[c] = (double)rn;
+      }
+    } else if (upd) {
+      // FP64: component by component (both vectors held at once would spill)
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const int64_t o = c * nv + v;
@@ -492,27 +528,12 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4) ? (K16 ? 5 : 6) : 4) k_c
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc += rs[c] * rs[c];
-    const int gi = a.gid[v];
+    if constexpr (sizeof(T) != 4) gi = a.gid[v];
     double Rg[9], rc[9], yc[9], ys[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Rg[i] = a.grainR[9 * gi + i];
     to_crystal(Rg, rs, rc);
     if constexpr (K16 != 0) {
-      // FP16, scaled: the tangent stream dominates the kernel's bytes, and this halves it.
-      // Entries 0-79 in ten 16-byte loads of eight, entry 80 in a 2-byte load
-      const uint4* K8 = reinterpret_cast<const uint4*>(a.K);
-      const __half* Kt = reinterpret_cast<const __half*>(a.K) + 80 * nv;
-      // (the packed words stay packed until their product: 41 registers instead of 81)
-      unsigned kw[41];
-#pragma unroll
-      for (int gq = 0; gq < 10; ++gq) {
-        const uint4 u = K8[(int64_t)gq * nv + v];
-        kw[4 * gq] = u.x;
-        kw[4 * gq + 1] = u.y;
-        kw[4 * gq + 2] = u.z;
-        kw[4 * gq + 3] = u.w;
-      }
-      kw[40] = (unsigned)__half_as_ushort(Kt[v]);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         double s = 0.0;
