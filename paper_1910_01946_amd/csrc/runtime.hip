@@ -546,6 +546,7 @@ struct RVE {
   int n[3];
   int64_t nvox = 0;
   double h = 0;
+  double c11_rms = 0;  // rms over the voxels of C11 (sets the FP64 form's residual floor)
   int n_grains = 0;
   MatDev mat;
   double rho0 = 0;
@@ -669,6 +670,14 @@ static void init_rve(Ctx& C, RVE& R, const rve_desc& d) {
         throw Error(RVE_EINVAL, "elastic constants of grain " + std::to_string(gi) + " are not positive definite");
     }
     upload(R.d_C, d.grain_elastic, sizeof(double) * 3 * (size_t)d.n_grains);
+    double s2 = 0.0;
+    for (int64_t v = 0; v < R.nvox; ++v) {
+      const double c11 = d.grain_elastic[3 * d.grain_of_voxel[v]];
+      s2 += c11 * c11;
+    }
+    R.c11_rms = std::sqrt(s2 / (double)R.nvox);
+  } else {
+    R.c11_rms = R.mat.C11;
   }
   upload(R.d_mat, &R.mat, sizeof(MatDev));
   upload(R.d_gid, d.grain_of_voxel, sizeof(int32_t) * R.nvox);
@@ -1253,16 +1262,27 @@ static void curl_plane64(const GridPlan& g, void* spec, const double* src, bool 
 // step brings the residual within kNewtonFloor of it ends the increment even when CG did not
 // converge: at the floor the right-hand side is rounding noise, to which the non-symmetric
 // tangent can respond with a breakdown or a growing residual, and no FP32 correction can
-// reduce the residual further.  The FP64 form has no such floor.
+// reduce the residual further.
+// The FP64 form's floor is set by F itself: each entry of F carries a rounding error of about
+// u64 (u64 = 2^-53, F of order one), which moves the stress by about C11 u64, far above the
+// transforms' u64 rms(P) when the stress is small against the stiffness (measured on a cu64
+// cell: Newton stagnates at 0.9 to 1.1 times u64 C11).  Its floor is u64 times the rms over the
+// voxels of their C11.  That estimate is only an upper bound where stiff phases are a small
+// part of the cell (a 1e6 stiffness-contrast cell converged to a fifth of it), so in FP64 it
+// does not stop CG; it only lets a Newton correction below newton_tol whose full step brings the
+// residual within kNewtonFloor64 of it end the increment after a CG that did not converge.
 constexpr double kU32 = 5.9604644775390625e-08;
+constexpr double kU64 = 1.1102230246251565e-16;
 constexpr double kCgFloor = 8.0;
 constexpr double kNewtonFloor = 32.0;
+constexpr double kNewtonFloor64 = 4.0;
 
 static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const double* Pbar, double dt, rve_step_stats& st,
                             const char** why) {
   const int64_t nv = R.nvox;
   const double n9 = 9.0 * (double)nv;
-  double p_floor = 0.0;  // u32 rms(P) at the current iterate (mixed form)
+  // rounding floor of the residual: u32 rms(P) at the current iterate (mixed form), u64 rms(C11)
+  double p_floor = w.fp32 ? 0.0 : kU64 * R.c11_rms;
   auto update_floor = [&]() {
     if (w.fp32) p_floor = kU32 * rms_of(C, R, false, R.P_work.as<double>(), 9 * nv);
   };
@@ -1284,7 +1304,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
   update_floor();
   for (int it = 0; it < C.opt.max_newton; ++it) {
     int done = 0;
-    const double cg_floor = kCgFloor * p_floor;
+    const double cg_floor = w.fp32 ? kCgFloor * p_floor : 0.0;
     const int ncg = run_cg(C, R, w, x, keep, done, false, cg_floor * cg_floor * n9);
     const CGState cg_end = *R.host_cg;
     st.cg_iters += ncg;
@@ -1315,7 +1335,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
         const double rr_t = run_residual(C, R, w, R.P_work.as<double>(), keep, Pbar, xo);
         st.residual_evals++;
         res_try = std::sqrt(rr_t / n9);
-        at_floor = w.fp32 && lam == 1.0 && dF <= C.opt.newton_tol && res_try <= kNewtonFloor * p_floor;
+        at_floor = lam == 1.0 && dF <= C.opt.newton_tol && res_try <= (w.fp32 ? kNewtonFloor : kNewtonFloor64) * p_floor;
         // a full correction below the tolerance is applied without a decrease test (the
         // residual is then at its rounding floor); otherwise the residual must not grow
         if (std::isfinite(res_try) &&
@@ -1332,7 +1352,7 @@ static int32_t newton_solve(Ctx& C, RVE& R, Work& w, const double* keep, const d
                    "[rve] newton %d: cg %d (code %d, rr/rr0 %.2e%s) |dF| %.3e lam %.4g res %.4e -> %.4e%s%s local_it %d "
                    "floor %.3e\n",
                    it + 1, ncg, done, cg_end.rr / cg_end.rr0, use_best ? ", best iterate" : "", dF, lam, res, res_try,
-                   accepted ? "" : " (line search failed)", at_floor ? " (at the FP32 floor)" : "",
+                   accepted ? "" : " (line search failed)", at_floor ? " (at the rounding floor)" : "",
                    st.local_iters_max, p_floor);
     if (!accepted) {
       *why = "residual line search failed";

@@ -93,6 +93,16 @@ def test_cu64_sgcp_at_8cubed_fp64_matches_oracle(lib):
     _check_gnd_fields(h, o, rves[0])
 
 
+def test_cu64_at_6cubed_fp64_to_its_rounding_floor_matches_oracle(lib):
+    """FP64 at newton_tol 1e-13 and CG 1e-12: the last Newton steps reach the residual's rounding
+    floor (about u64 C11, set by the rounding of F), where CG on the noise breaks down or stalls;
+    the increment must still end there, through the floor rule, and agree with the oracle."""
+    rves, path = synth.workload("cu64", n_override=6, n_inc_override=50)
+    o, h, out = _run_both(lib, rves[0], path, 2, newton_tol=1e-13, cg_tol=1e-12)
+    for Po, Pg, Fo, Fg in out:
+        assert np.max(np.abs(Pg - Po)) <= 1e-10 * np.abs(Po).max()
+
+
 _MIXED_ORACLE = {}
 
 
