@@ -613,7 +613,7 @@ def main():
         summarize_trace(args.summarize_trace, args.workload, args.profiles_dir, args.bench_json)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only (this build has no multi-GPU "
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the library has no multi-GPU "
                                    "path); run it with --gpus 1"}))
         sys.exit(2)
     if args.copy_calibration:
